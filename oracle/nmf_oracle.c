@@ -191,8 +191,10 @@ int orc_bpp(int k, const double* G, const double* f, double* x, uint64_t* F_io, 
   const uint64_t all = (k == 64) ? ~0ull : ((1ull << k) - 1ull);
   uint64_t pinned = orc_pinned_set(k, G);
   int st = pinned ? ORC_ST_PINNED : 0;
-  int warm = (*F_io & all) != 0;
+  /* a warm start is an initial passive set that is nonempty once the
+   * pinned indices are removed from it */
   uint64_t F = *F_io & all & ~pinned;
+  int warm = F != 0;
   int alpha = 3, beta = k + 1, rounds = 0, since_start = 0;
   double y[ORC_MAXK];
   for (;;) {
