@@ -1,0 +1,231 @@
+/*
+ * libnmf -- ANLS-BPP nonnegative matrix factorisation on one MI355X (gfx950).
+ *
+ * Problem (Kannan, Ballard & Park, Eq. NMF): given A (m x n), find W >= 0
+ * (m x k) and H >= 0 (k x n) minimising ||A - W H||_F^2, by the alternating
+ * scheme of Eq. two-block / Algorithm 1: W from (H H^T, A H^T), then H from
+ * (W^T W, W^T A), each row of W and column of H being an independent
+ * nonnegative least-squares problem (Eq. single NLS) solved by block principal
+ * pivoting (Section "Block Principal Pivoting").
+ *
+ * Conventions for every entry point:
+ *  - Pointers named as device pointers are device memory, owned and allocated
+ *    by the caller; the library never allocates or frees device memory.
+ *  - Matrices are row-major with an explicit leading dimension (in elements).
+ *    H is always passed transposed, as Ht (n x k), so that both factor
+ *    updates are "one problem per row of an (rows x k) matrix".
+ *  - Scratch space is a caller-provided device buffer `ws` of `ws_bytes`,
+ *    sized by the matching *_workspace_bytes query (256-byte aligned).
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL means
+ *    the default stream) and is complete only after the stream is
+ *    synchronised.  No entry point synchronises the stream.
+ *  - Return value: NMF_OK, or an error code; on error nothing has been
+ *    enqueued unless the code is NMF_EHIP, and nmf_last_error() returns a
+ *    message (thread-local).  Argument checks are done on the host before any
+ *    device call.
+ *  - k (the rank) must satisfy 1 <= k <= 64.
+ */
+#ifndef LIBNMF_H
+#define LIBNMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define NMF_OK 0
+#define NMF_EINVAL 1        /* bad size, leading dimension, null pointer, k */
+#define NMF_EUNSUPPORTED 2  /* a combination this build does not implement */
+#define NMF_EHIP 3          /* a HIP runtime call or kernel launch failed */
+#define NMF_EWORKSPACE 4    /* ws too small (query *_workspace_bytes) */
+
+/* ---- enumerations --------------------------------------------------------- */
+#define NMF_F32 0     /* right-hand sides in FP32 (MFMA / SpMM) */
+#define NMF_BF16X3 1  /* right-hand sides as hi*hi + hi*lo + lo*hi BF16 MFMA, FP32 accumulate */
+
+#define NMF_SIDE_W 0  /* R (m x k) = A  * Ht : right-hand side of the W update */
+#define NMF_SIDE_H 1  /* R (n x k) = A^T * W : (W^T A)^T, right-hand side of the H update */
+
+#define NMF_DENSE 0
+#define NMF_CSR 1
+
+#define NMF_OBJ_DIRECT 0  /* ||A - W H||_F from A itself (dense) or its nonzeros (CSR) */
+#define NMF_OBJ_TRACE 1   /* ||A||^2 - 2 <A^T W, H^T> + <W^T W, H H^T>, FP64, monitoring */
+
+#define NMF_WARM_COLD 0     /* every BPP starts from the empty passive set */
+#define NMF_WARM_PREV 1     /* start from the previous iteration's passive set */
+#define NMF_WARM_LEARNED 2  /* start from the warm-start network's prediction */
+
+/* per-problem BPP status bits */
+#define NMF_BPP_WARM_FALLBACK 1  /* warm start restarted cold after warm_cap rounds */
+#define NMF_BPP_CAPPED 2         /* KKT still violated after max_rounds; x clamped to >= 0 */
+#define NMF_BPP_PINNED 4         /* an index with G_ii <= 1e-14 max G_ll was held at 0 */
+#define NMF_BPP_SINGULAR 8       /* a passive-subset pivot <= 1e-12 G_jj; index held at 0 */
+
+/* BPP counters (device array of NMF_BPP_COUNTERS uint64, accumulated, optional):
+ * [0] KKT checks (rounds), [1] passive-set solves (rounds with F nonempty),
+ * [2] sum |F|, [3] sum |F|^2, [4] sum |F|^3, each over the solves. */
+#define NMF_BPP_COUNTERS 5
+
+const char* nmf_last_error(void);
+const char* nmf_version(void);
+
+/* ---- Gram matrix ----------------------------------------------------------
+ * G = X^T X (k x k, FP64, both triangles, ld k) for X (rows x k, FP32,
+ * leading dimension ldx >= k).  With X = Ht this is H H^T, with X = W it is
+ * W^T W (Algorithm 1, both updates; the local Gram of Algorithm 3).  FP32
+ * products are exact in FP64 and are summed in FP64 in a fixed order, so the
+ * result is deterministic.  rows == 0 gives G = 0. */
+int nmf_gram_workspace_bytes(int64_t rows, int k, size_t* bytes);
+int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* ws, size_t ws_bytes,
+             void* stream);
+
+/* ---- dense right-hand sides -----------------------------------------------
+ * side NMF_SIDE_W: R (m x k) = A (m x n) * Y with Y = Ht (n x k), i.e. A H^T.
+ * side NMF_SIDE_H: R (n x k) = A^T * Y with Y = W (m x k), i.e. (W^T A)^T.
+ * A: FP32 m x n, leading dimension lda >= n (device).
+ * prec NMF_F32: FP32 MFMA with FP32 accumulation (side H: split over rows of
+ *   A with a deterministic FP64 sum of the FP32 partials).
+ * prec NMF_BF16X3: the operand whose columns are contracted is given as two
+ *   BF16 planes from nmf_split_bf16: for side W the planes of A (m x n), for
+ *   side H the planes of A^T (n x m), leading dimension ldb.  Y is split in
+ *   the workspace each call; R = hi*hi + hi*lo + lo*hi (lo*lo dropped),
+ *   FP32 accumulation.  A itself is not read in this mode and may be NULL.
+ * R: FP32, leading dimension ldr >= k (device). */
+int nmf_rhs_dense_workspace_bytes(int side, int64_t m, int64_t n, int k, int prec, size_t* bytes);
+int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda,
+                  const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y, int64_t ldy,
+                  float* R, int64_t ldr, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* One-time split of an FP32 matrix X (rows x cols, ldx) into BF16 planes:
+ * hi = bf16_rne(x), lo = bf16_rne(x - hi) (x - hi is exact in FP32).
+ * transpose = 0 writes planes of X (rows x cols, ld ldo); transpose = 1 writes
+ * the planes of X^T (cols x rows, ld ldo).  hi, lo: device uint16 buffers. */
+int nmf_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* hi, uint16_t* lo,
+                   int64_t ldo, int transpose, void* stream);
+
+/* ---- sparse right-hand side -----------------------------------------------
+ * R (rows x k) = A_csr (rows x cols) * Y (cols x k, ldy >= k).  Pass CSR(A)
+ * with Y = Ht for A H^T, CSR(A^T) with Y = W for (W^T A)^T.  rowptr int64
+ * (rows + 1), colidx int32 in [0, cols), vals FP32.  One wavefront per row,
+ * products accumulated in FP64 in storage order, stored as FP32. */
+int nmf_rhs_csr(int64_t rows, int64_t cols, int k, const int64_t* rowptr, const int32_t* colidx,
+                const float* vals, const float* Y, int64_t ldy, float* R, int64_t ldr, void* stream);
+
+/* ---- batched NNLS by block principal pivoting -----------------------------
+ * For each row b < batch: X[b] = argmin_{x >= 0} 1/2 x^T G x - R[b]^T x,
+ * i.e. min ||C x - c||^2 with C^T C = G, C^T c = R[b] (Eq. single NLS, KKT
+ * conditions Eq. KKT).  G: k x k FP64, symmetric (device).  R: FP32 rows,
+ * ldr >= k; X: FP32 rows, ldx >= k (X may alias R only if ldx == ldr).
+ * mask_in (optional): initial passive sets (bit i = index i passive); NULL
+ * or an all-zero mask is a cold start.  mask_out (optional): final passive
+ * sets (may alias mask_in).  rounds (optional): KKT checks per problem
+ * (saturating at 255).  status (optional): NMF_BPP_* bits per problem.
+ * max_rounds >= 1 caps the KKT checks; warm_cap >= 1 is the number of rounds a
+ * nonempty mask_in gets before the cold restart.  counters (optional): see
+ * NMF_BPP_COUNTERS; accumulated (not cleared).  The passive-subset systems
+ * are solved in FP64 (symmetric elimination in index order).  Returns
+ * NMF_OK even when some problems are capped (see status). */
+int nnls_bpp_batched(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X,
+                     int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds,
+                     uint8_t* status, int max_rounds, int warm_cap, uint64_t* counters, void* stream);
+
+/* ---- the data matrix ------------------------------------------------------- */
+typedef struct nmf_matrix {
+  int kind;                 /* NMF_DENSE or NMF_CSR */
+  int64_t m, n;
+  /* dense */
+  const float* A;           /* m x n FP32, leading dimension lda (device) */
+  int64_t lda;
+  const uint16_t* A_hi;     /* BF16X3 only: planes of A   (m x n, ld ld_hl) */
+  const uint16_t* A_lo;
+  int64_t ld_hl;
+  const uint16_t* At_hi;    /* BF16X3 only: planes of A^T (n x m, ld ld_hl_t) */
+  const uint16_t* At_lo;
+  int64_t ld_hl_t;
+  /* sparse */
+  int64_t nnz;              /* number of stored entries (both CSR copies) */
+  const int64_t* rowptr;    /* CSR(A):   m + 1 */
+  const int32_t* colidx;
+  const float* vals;
+  const int64_t* rowptr_t;  /* CSR(A^T): n + 1 */
+  const int32_t* colidx_t;
+  const float* vals_t;
+  /* ||A||_F^2 (device FP64 scalar, from nmf_fro2); needed by NMF_OBJ_TRACE and
+   * by the per-iteration objective of nmf_anls_iter */
+  const double* fro2;
+} nmf_matrix;
+
+/* ||A||_F^2 in FP64 into *out (device). */
+int nmf_fro2_workspace_bytes(const nmf_matrix* A, size_t* bytes);
+int nmf_fro2(const nmf_matrix* A, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- objective ----------------------------------------------------------------
+ * r = ||A - W H||_F / ||A||_F (Eq. NMF), written to out[0] (device); out[1] =
+ * ||A - W H||_F^2 and out[2] = ||A||_F^2.  W: m x k, Ht: n x k (FP32, ld k).
+ * NMF_OBJ_DIRECT: dense A is read once and W H is formed tile by tile (FP32
+ *   MFMA) with FP64 sums; CSR uses ||A||^2 - 2 sum_nnz a_ij (WH)_ij +
+ *   <W^T W, H H^T> in FP64.  G_W, G_H, R_H are ignored (may be NULL).
+ * NMF_OBJ_TRACE: uses A->fro2 and the FP64 Grams G_W = W^T W, G_H = H H^T
+ *   and R_H = A^T W (n x k, ld k) of the current factors. */
+int nmf_objective_workspace_bytes(const nmf_matrix* A, int k, int mode, size_t* bytes);
+int nmf_objective(const nmf_matrix* A, int k, const float* W, const float* Ht, int mode,
+                  const double* G_W, const double* G_H, const float* R_H, double* out, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ---- the ANLS driver --------------------------------------------------------- */
+typedef struct nmf_opts {
+  int prec;             /* NMF_F32 or NMF_BF16X3 (dense only) */
+  int warm;             /* NMF_WARM_COLD / NMF_WARM_PREV / NMF_WARM_LEARNED */
+  int max_rounds;       /* BPP round cap (e.g. 100) */
+  int warm_cap;         /* rounds a warm start gets before its cold restart */
+  int trace_objective;  /* 1: record r after each half-step (TRACE, FP64) */
+  int reset_masks;      /* 1: clear the stored passive sets before the first iteration */
+  const float* net_w;   /* NMF_WARM_LEARNED: W-side network parameters (device) */
+  const float* net_h;   /* NMF_WARM_LEARNED: H-side network parameters (device) */
+  /* sample collection for training the network (optional, device buffers):
+   * in every half-step the problems b with b % stride == 0 store their
+   * features (2k FP32) and final passive set; the W-side samples of the
+   * t-th iteration of this call go to positions
+   * coll_off_w + t * ceil(m / collect_stride_w) + b / collect_stride_w
+   * (H side likewise with n); positions >= the capacity are dropped. */
+  int collect;
+  int collect_stride_w;
+  int collect_stride_h;
+  float* coll_phi_w;
+  uint64_t* coll_mask_w;
+  int64_t coll_cap_w;
+  int64_t coll_off_w;
+  float* coll_phi_h;
+  uint64_t* coll_mask_h;
+  int64_t coll_cap_h;
+  int64_t coll_off_h;
+} nmf_opts;
+
+/* Per-iteration statistics, written to a device array of `iters` entries. */
+typedef struct nmf_iter_stats {
+  double r_half;        /* relative objective after the W update (trace form) */
+  double r_full;        /* relative objective after the H update (trace form) */
+  uint64_t bpp_w[NMF_BPP_COUNTERS];  /* counters of the W half-step */
+  uint64_t bpp_h[NMF_BPP_COUNTERS];  /* counters of the H half-step */
+  uint64_t capped;      /* problems with NMF_BPP_CAPPED in this iteration */
+  uint64_t fallback;    /* problems with NMF_BPP_WARM_FALLBACK */
+} nmf_iter_stats;
+
+/* Runs `iters` iterations of Algorithm 1 (W update, then H update) in place
+ * on W (m x k) and Ht (n x k), FP32 device buffers with ld k.  The workspace
+ * holds the Gram matrices, right-hand sides and the passive sets that carry
+ * over between calls for NMF_WARM_PREV (keep ws alive and unchanged between
+ * calls; set reset_masks on the first call).  stats: device array of `iters`
+ * nmf_iter_stats (optional). */
+int nmf_anls_workspace_bytes(const nmf_matrix* A, int k, const nmf_opts* o, size_t* bytes);
+int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, int iters, const nmf_opts* o,
+                  nmf_iter_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBNMF_H */

@@ -1,0 +1,319 @@
+"""Python binding of libnmf (ctypes).  Argument marshalling only: every step
+of the computation runs in the HIP kernels of libnmf.so.  torch supplies device
+memory and the current stream.  There is no fallback: if libnmf.so is missing
+or was not built for this GPU, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnmf.so")
+
+NMF_OK, NMF_EINVAL, NMF_EUNSUPPORTED, NMF_EHIP, NMF_EWORKSPACE = 0, 1, 2, 3, 4
+NMF_F32, NMF_BF16X3 = 0, 1
+NMF_SIDE_W, NMF_SIDE_H = 0, 1
+NMF_DENSE, NMF_CSR = 0, 1
+NMF_OBJ_DIRECT, NMF_OBJ_TRACE = 0, 1
+NMF_WARM_COLD, NMF_WARM_PREV, NMF_WARM_LEARNED = 0, 1, 2
+NMF_BPP_WARM_FALLBACK, NMF_BPP_CAPPED, NMF_BPP_PINNED, NMF_BPP_SINGULAR = 1, 2, 4, 8
+NMF_BPP_COUNTERS = 5
+
+
+class NmfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libnmf error {code}: {msg}")
+        self.code = code
+
+
+vp = ctypes.c_void_p
+i64 = ctypes.c_int64
+ci = ctypes.c_int
+
+
+class nmf_matrix(ctypes.Structure):
+    _fields_ = [("kind", ci), ("m", i64), ("n", i64),
+                ("A", vp), ("lda", i64),
+                ("A_hi", vp), ("A_lo", vp), ("ld_hl", i64),
+                ("At_hi", vp), ("At_lo", vp), ("ld_hl_t", i64),
+                ("nnz", i64),
+                ("rowptr", vp), ("colidx", vp), ("vals", vp),
+                ("rowptr_t", vp), ("colidx_t", vp), ("vals_t", vp),
+                ("fro2", vp)]
+
+
+class nmf_opts(ctypes.Structure):
+    _fields_ = [("prec", ci), ("warm", ci), ("max_rounds", ci), ("warm_cap", ci),
+                ("trace_objective", ci), ("reset_masks", ci),
+                ("net_w", vp), ("net_h", vp),
+                ("collect", ci), ("collect_stride_w", ci), ("collect_stride_h", ci),
+                ("coll_phi_w", vp), ("coll_mask_w", vp), ("coll_cap_w", i64), ("coll_off_w", i64),
+                ("coll_phi_h", vp), ("coll_mask_h", vp), ("coll_cap_h", i64), ("coll_off_h", i64)]
+
+
+class nmf_iter_stats(ctypes.Structure):
+    _fields_ = [("r_half", ctypes.c_double), ("r_full", ctypes.c_double),
+                ("bpp_w", ctypes.c_uint64 * NMF_BPP_COUNTERS),
+                ("bpp_h", ctypes.c_uint64 * NMF_BPP_COUNTERS),
+                ("capped", ctypes.c_uint64), ("fallback", ctypes.c_uint64)]
+
+
+STATS_WORDS = ctypes.sizeof(nmf_iter_stats) // 8
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1509_09313_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sz = ctypes.POINTER(ctypes.c_size_t)
+        M = ctypes.POINTER(nmf_matrix)
+        O = ctypes.POINTER(nmf_opts)
+        sig = {
+            "nmf_last_error": ([], ctypes.c_char_p),
+            "nmf_version": ([], ctypes.c_char_p),
+            "nmf_gram_workspace_bytes": ([i64, ci, sz], ci),
+            "nmf_gram": ([i64, ci, vp, i64, vp, vp, ctypes.c_size_t, vp], ci),
+            "nmf_rhs_dense_workspace_bytes": ([ci, i64, i64, ci, ci, sz], ci),
+            "nmf_rhs_dense": ([ci, i64, i64, ci, vp, i64, vp, vp, i64, vp, i64, vp, i64, ci, vp, ctypes.c_size_t,
+                               vp], ci),
+            "nmf_split_bf16": ([i64, i64, vp, i64, vp, vp, i64, ci, vp], ci),
+            "nmf_rhs_csr": ([i64, i64, ci, vp, vp, vp, vp, i64, vp, i64, vp], ci),
+            "nnls_bpp_batched": ([ci, i64, vp, vp, i64, vp, i64, vp, vp, vp, vp, ci, ci, vp, vp], ci),
+            "nmf_fro2_workspace_bytes": ([M, sz], ci),
+            "nmf_fro2": ([M, vp, vp, ctypes.c_size_t, vp], ci),
+            "nmf_objective_workspace_bytes": ([M, ci, ci, sz], ci),
+            "nmf_objective": ([M, ci, vp, vp, ci, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ci),
+            "nmf_anls_workspace_bytes": ([M, ci, O, sz], ci),
+            "nmf_anls_iter": ([M, ci, vp, vp, ci, O, vp, vp, ctypes.c_size_t, vp], ci),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != NMF_OK:
+        raise NmfError(rc, lib().nmf_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ws(nbytes):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() == 2 and t.numel() > 0 and t.stride(1) != 1:
+        raise ValueError(f"{name} must be row-major with unit column stride")
+    return t
+
+
+def _ld(t):
+    return t.stride(0) if t.dim() == 2 else t.shape[-1]
+
+
+def version() -> str:
+    return lib().nmf_version().decode()
+
+
+def nmf_gram(X, G=None):
+    """G = X^T X (k x k, float64) for X (rows x k, float32)."""
+    _dev(X, torch.float32, "X")
+    rows, k = X.shape
+    if G is None:
+        G = torch.empty((k, k), dtype=torch.float64, device="cuda")
+    nb = ctypes.c_size_t(0)
+    _check(lib().nmf_gram_workspace_bytes(rows, k, ctypes.byref(nb)))
+    ws = _ws(nb.value)
+    _check(lib().nmf_gram(rows, k, _ptr(X), _ld(X), _ptr(G), _ptr(ws), nb.value, _stream()))
+    return G
+
+
+def nmf_split_bf16(X, transpose=False):
+    """(hi, lo) int16 planes of X (or of X^T if transpose)."""
+    _dev(X, torch.float32, "X")
+    rows, cols = X.shape
+    shape = (cols, rows) if transpose else (rows, cols)
+    hi = torch.empty(shape, dtype=torch.int16, device="cuda")
+    lo = torch.empty(shape, dtype=torch.int16, device="cuda")
+    _check(lib().nmf_split_bf16(rows, cols, _ptr(X), _ld(X), _ptr(hi), _ptr(lo), shape[1], int(transpose),
+                                _stream()))
+    return hi, lo
+
+
+def nmf_rhs_dense(side, A, Y, R=None, prec=NMF_F32, B_hi=None, B_lo=None, m=None, n=None):
+    """side W: R = A @ Y (Y = Ht); side H: R = A^T @ Y (Y = W).  For BF16X3
+    pass the planes of A (side W) or of A^T (side H) as B_hi / B_lo."""
+    _dev(Y, torch.float32, "Y")
+    k = Y.shape[1]
+    if A is not None:
+        _dev(A, torch.float32, "A")
+        m, n = A.shape
+    rows_out = m if side == NMF_SIDE_W else n
+    if R is None:
+        R = torch.empty((rows_out, k), dtype=torch.float32, device="cuda")
+    nb = ctypes.c_size_t(0)
+    _check(lib().nmf_rhs_dense_workspace_bytes(side, m, n, k, prec, ctypes.byref(nb)))
+    ws = _ws(nb.value)
+    ldb = _ld(B_hi) if B_hi is not None else (n if side == NMF_SIDE_W else m)
+    _check(lib().nmf_rhs_dense(side, m, n, k, _ptr(A), _ld(A) if A is not None else n, _ptr(B_hi), _ptr(B_lo), ldb,
+                               _ptr(Y), _ld(Y), _ptr(R), _ld(R), prec, _ptr(ws), nb.value, _stream()))
+    return R
+
+
+def nmf_rhs_csr(rowptr, colidx, vals, Y, rows, cols, R=None):
+    _dev(Y, torch.float32, "Y")
+    k = Y.shape[1]
+    if R is None:
+        R = torch.empty((rows, k), dtype=torch.float32, device="cuda")
+    _check(lib().nmf_rhs_csr(rows, cols, k, _ptr(rowptr), _ptr(colidx), _ptr(vals), _ptr(Y), _ld(Y), _ptr(R), _ld(R),
+                             _stream()))
+    return R
+
+
+def nnls_bpp_batched(G, R, X=None, mask_in=None, mask_out=None, rounds=None, status=None, max_rounds=100,
+                     warm_cap=8, counters=None):
+    """Rows of R (batch x k, float32) against G (k x k, float64).  Returns
+    (X, mask_out, rounds, status); masks are int64 tensors holding the uint64
+    bit patterns."""
+    _dev(G, torch.float64, "G")
+    _dev(R, torch.float32, "R")
+    batch, k = R.shape
+    if X is None:
+        X = torch.empty((batch, k), dtype=torch.float32, device="cuda")
+    if mask_out is None:
+        mask_out = torch.empty(batch, dtype=torch.int64, device="cuda")
+    if rounds is None:
+        rounds = torch.empty(batch, dtype=torch.uint8, device="cuda")
+    if status is None:
+        status = torch.empty(batch, dtype=torch.uint8, device="cuda")
+    _check(lib().nnls_bpp_batched(k, batch, _ptr(G), _ptr(R), _ld(R), _ptr(X), _ld(X), _ptr(mask_in), _ptr(mask_out),
+                                  _ptr(rounds), _ptr(status), max_rounds, warm_cap, _ptr(counters), _stream()))
+    return X, mask_out, rounds, status
+
+
+class Matrix:
+    """Owner of the device tensors behind one nmf_matrix."""
+
+    def __init__(self, *, dense=None, csr=None, csr_t=None, shape=None, split=False):
+        self.keep = []
+        s = nmf_matrix()
+        if dense is not None:
+            _dev(dense, torch.float32, "A")
+            self.m, self.n = dense.shape
+            s.kind, s.m, s.n, s.A, s.lda = NMF_DENSE, self.m, self.n, dense.data_ptr(), _ld(dense)
+            self.keep.append(dense)
+            self.A = dense
+        else:
+            self.m, self.n = shape
+            rp, ci_, va = csr
+            rpt, cit, vat = csr_t
+            s.kind, s.m, s.n = NMF_CSR, self.m, self.n
+            s.nnz = int(va.numel())
+            s.rowptr, s.colidx, s.vals = rp.data_ptr(), ci_.data_ptr(), va.data_ptr()
+            s.rowptr_t, s.colidx_t, s.vals_t = rpt.data_ptr(), cit.data_ptr(), vat.data_ptr()
+            self.keep += [rp, ci_, va, rpt, cit, vat]
+            self.A = None
+        self.s = s
+        self.fro2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.s.fro2 = self.fro2.data_ptr()
+        nb = ctypes.c_size_t(0)
+        _check(lib().nmf_fro2_workspace_bytes(ctypes.byref(self.s), ctypes.byref(nb)))
+        ws = _ws(nb.value)
+        _check(lib().nmf_fro2(ctypes.byref(self.s), _ptr(self.fro2), _ptr(ws), nb.value, _stream()))
+        if split:
+            self.add_split()
+
+    def add_split(self):
+        hi, lo = nmf_split_bf16(self.A)
+        hit, lot = nmf_split_bf16(self.A, transpose=True)
+        self.keep += [hi, lo, hit, lot]
+        self.planes = (hi, lo, hit, lot)
+        self.s.A_hi, self.s.A_lo, self.s.ld_hl = hi.data_ptr(), lo.data_ptr(), _ld(hi)
+        self.s.At_hi, self.s.At_lo, self.s.ld_hl_t = hit.data_ptr(), lot.data_ptr(), _ld(hit)
+
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def nmf_objective(M: Matrix, W, Ht, mode=NMF_OBJ_DIRECT, G_W=None, G_H=None, R_H=None):
+    """Tensor [r, ||A-WH||^2, ||A||^2] (float64, device)."""
+    k = W.shape[1]
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    nb = ctypes.c_size_t(0)
+    _check(lib().nmf_objective_workspace_bytes(M.ref(), k, mode, ctypes.byref(nb)))
+    ws = _ws(nb.value)
+    _check(lib().nmf_objective(M.ref(), k, _ptr(W), _ptr(Ht), mode, _ptr(G_W), _ptr(G_H), _ptr(R_H), _ptr(out),
+                               _ptr(ws), nb.value, _stream()))
+    return out
+
+
+def make_opts(prec=NMF_F32, warm=NMF_WARM_COLD, max_rounds=100, warm_cap=8, trace=True, reset_masks=True,
+              net_w=None, net_h=None):
+    o = nmf_opts()
+    o.prec, o.warm, o.max_rounds, o.warm_cap = prec, warm, max_rounds, warm_cap
+    o.trace_objective, o.reset_masks = int(trace), int(reset_masks)
+    o.net_w = None if net_w is None else net_w.data_ptr()
+    o.net_h = None if net_h is None else net_h.data_ptr()
+    return o
+
+
+class Anls:
+    """Keeps the workspace of nmf_anls_iter alive between calls (the stored
+    passive sets carry over for the previous-iterate warm start)."""
+
+    def __init__(self, M: Matrix, k: int, opts: nmf_opts):
+        self.M, self.k, self.opts = M, k, opts
+        nb = ctypes.c_size_t(0)
+        _check(lib().nmf_anls_workspace_bytes(M.ref(), k, ctypes.byref(opts), ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = _ws(nb.value)
+
+    def run(self, W, Ht, iters, stats=None):
+        _dev(W, torch.float32, "W")
+        _dev(Ht, torch.float32, "Ht")
+        _check(lib().nmf_anls_iter(self.M.ref(), self.k, _ptr(W), _ptr(Ht), iters, ctypes.byref(self.opts),
+                                   _ptr(stats), _ptr(self.ws), self.ws_bytes, _stream()))
+        return stats
+
+
+def new_stats(iters):
+    return torch.zeros((iters, STATS_WORDS), dtype=torch.int64, device="cuda")
+
+
+def decode_stats(stats):
+    """Host dicts from a stats tensor."""
+    raw = stats.cpu().contiguous()
+    arr = (nmf_iter_stats * raw.shape[0]).from_buffer_copy(raw.numpy().tobytes())
+    out = []
+    for s in arr:
+        out.append(dict(r_half=s.r_half, r_full=s.r_full, bpp_w=list(s.bpp_w), bpp_h=list(s.bpp_h),
+                        capped=s.capped, fallback=s.fallback))
+    return out
+
+
+def nmf_anls_iter(M: Matrix, k, W, Ht, iters, opts=None, stats=None):
+    opts = opts or make_opts()
+    runner = Anls(M, k, opts)
+    runner.run(W, Ht, iters, stats)
+    return runner

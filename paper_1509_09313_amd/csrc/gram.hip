@@ -1,0 +1,144 @@
+// Gram matrix G = X^T X for a tall FP32 matrix X (rows x k), FP64 result.
+//
+// The local Gram products of Algorithm 1 / Algorithm 3 (H H^T from Ht, W^T W
+// from W).  Work is HBM-streaming over X (rows * k * 4 bytes) with k^2/2 FP64
+// multiply-adds per row: each block stages a tile of rows in LDS and every
+// thread accumulates a 4 x 4 block of the upper triangle of G for one slice of
+// the tile's rows; slices and then blocks are combined in a fixed order, so
+// the FP64 result does not depend on scheduling.
+#include "nmf_common.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTileRows = 128;
+constexpr int kMaxBlocks = 512;
+
+__global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, const float* __restrict__ X,
+                                                           int64_t ldx, double* __restrict__ partial) {
+  __shared__ float tile[kTileRows][64 + 4];
+  __shared__ double red[kThreads * 4];  // slice reduction scratch (re-used)
+  const int kp = (k + 3) & ~3;
+  const int kt = kp >> 2;                 // 4-wide column blocks
+  const int npairs = kt * (kt + 1) / 2;   // upper-triangular block pairs
+  const int slices = kThreads / npairs;   // >= 1 because npairs <= 136
+  const int t = threadIdx.x;
+  const int slice = t / npairs;
+  const int pair = t - slice * npairs;
+  const bool active = slice < slices;
+  // pair -> (bi, bj) with bi <= bj
+  int bi = 0, rem = pair;
+  while (rem >= kt - bi) { rem -= kt - bi; ++bi; }
+  const int bj = bi + rem;
+
+  double acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+
+  const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
+  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int64_t r0 = tl * kTileRows;
+    __syncthreads();
+    for (int idx = t; idx < kTileRows * kp; idx += kThreads) {
+      const int rr = idx / kp, cc = idx - rr * kp;
+      const int64_t r = r0 + rr;
+      tile[rr][cc] = (r < rows && cc < k) ? X[r * ldx + cc] : 0.0f;
+    }
+    __syncthreads();
+    if (active) {
+      const int nr = (int)((rows - r0) < kTileRows ? (rows - r0) : kTileRows);
+      for (int rr = slice; rr < nr; rr += slices) {
+        const float4 a = *reinterpret_cast<const float4*>(&tile[rr][4 * bi]);
+        const float4 b = *reinterpret_cast<const float4*>(&tile[rr][4 * bj]);
+        const double av[4] = {a.x, a.y, a.z, a.w};
+        const double bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) acc[ii * 4 + jj] += av[ii] * bv[jj];
+      }
+    }
+  }
+  // combine slices in order, four entries of the 4 x 4 block at a time
+  double* out = partial + (int64_t)blockIdx.x * k * k;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[t * 4 + e] = acc[q * 4 + e];
+    }
+    __syncthreads();
+    if (active && slice == 0) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int sl = 0; sl < slices; ++sl)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[e] += red[(sl * npairs + pair) * 4 + e];
+      const int ii = q;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = 4 * bi + ii, gj = 4 * bj + e;
+        if (gi < k && gj < k) {
+          out[gi * k + gj] = s[e];
+          out[gj * k + gi] = s[e];
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_gram_reduce(int k, int nblocks, const double* __restrict__ partial, double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * k * k + e];
+  G[e] = s;
+}
+
+int gram_blocks(int64_t rows) {
+  const int64_t tiles = (rows + kTileRows - 1) / kTileRows;
+  return (int)(tiles < 1 ? 1 : (tiles > kMaxBlocks ? kMaxBlocks : tiles));
+}
+
+}  // namespace
+
+namespace nmf {
+
+int gram_plan(int64_t rows, int k, Carver& c, double** partial, int* nblocks) {
+  *nblocks = gram_blocks(rows);
+  *partial = c.take<double>((size_t)(*nblocks) * k * k);
+  return NMF_OK;
+}
+
+int gram_launch(int64_t rows, int k, const float* X, int64_t ldx, double* G, double* partial, int nblocks,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_partial, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial);
+  NMF_TRY(launch_status("gram partial"));
+  hipLaunchKernelGGL(k_gram_reduce, dim3((k * k + 255) / 256), dim3(256), 0, s, k, nblocks, partial, G);
+  return launch_status("gram reduce");
+}
+
+}  // namespace nmf
+
+extern "C" int nmf_gram_workspace_bytes(int64_t rows, int k, size_t* bytes) {
+  if (!bytes || rows < 0 || !nmf::valid_k(k)) return nmf::fail(NMF_EINVAL, "nmf_gram_workspace_bytes: bad arguments");
+  nmf::Carver c(nullptr, 0);
+  double* p;
+  int nb;
+  nmf::gram_plan(rows, k, c, &p, &nb);
+  *bytes = c.off;
+  return NMF_OK;
+}
+
+extern "C" int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!nmf::valid_k(k)) return nmf::fail(NMF_EINVAL, "nmf_gram: k=%d outside [1,64]", k);
+  if (rows < 0 || ldx < k) return nmf::fail(NMF_EINVAL, "nmf_gram: rows=%lld ldx=%lld", (long long)rows, (long long)ldx);
+  if (!G || (rows > 0 && !X)) return nmf::fail(NMF_EINVAL, "nmf_gram: null pointer");
+  nmf::Carver c(ws, ws_bytes);
+  double* partial;
+  int nb;
+  nmf::gram_plan(rows, k, c, &partial, &nb);
+  if (!c.fits() || !ws) return nmf::fail(NMF_EWORKSPACE, "nmf_gram: workspace %zu < %zu bytes", ws_bytes, c.off);
+  return nmf::gram_launch(rows, k, X, ldx, G, partial, nb, nmf::as_stream(stream));
+}

@@ -1,0 +1,99 @@
+// Internal helpers shared by the libnmf translation units: error reporting,
+// workspace carving, launch checks and small device utilities.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "libnmf.h"
+
+namespace nmf {
+
+// Thread-local error message behind nmf_last_error().
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+inline int launch_status(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(NMF_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return NMF_OK;
+}
+
+#define NMF_TRY(expr)          \
+  do {                         \
+    const int _rc = (expr);    \
+    if (_rc != NMF_OK) return _rc; \
+  } while (0)
+
+// Carves 256-byte-aligned sub-buffers out of a caller workspace.  With a null
+// base it only measures, so one routine both sizes and lays out a workspace.
+struct Carver {
+  char* base;
+  size_t cap;
+  size_t off = 0;
+  Carver(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  bool fits() const { return off <= cap; }
+};
+
+inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+inline bool valid_k(int k) { return k >= 1 && k <= 64; }
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---- internal launchers shared between translation units -------------------
+int gram_plan(int64_t rows, int k, Carver& c, double** partial, int* nblocks);
+int gram_launch(int64_t rows, int k, const float* X, int64_t ldx, double* G, double* partial,
+                int nblocks, hipStream_t s);
+
+int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, void** scratch);
+int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda,
+                     const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y,
+                     int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s);
+
+int rhs_csr_launch(int64_t rows, int64_t cols, int k, const int64_t* rowptr, const int32_t* colidx,
+                   const float* vals, const float* Y, int64_t ldy, float* R, int64_t ldr,
+                   hipStream_t s);
+
+int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X,
+               int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds,
+               uint8_t* status, int max_rounds, int warm_cap, uint64_t* counters, hipStream_t s);
+
+// Zero-fills a rows x cols FP32 block with leading dimension ld (a kernel, so
+// it is safe inside captured graphs).
+int zero_f32(float* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t s);
+
+// Deterministic FP64 dot products  out[0] = sum_i a[i] * b[i]  over `len`
+// elements of two FP32 arrays (a, b) or FP64 arrays.
+int dot_plan(int64_t len, Carver& c, double** partial, int* nblocks);
+int dot_f32_launch(int64_t len, const float* a, const float* b, double* out, double* partial,
+                   int nblocks, hipStream_t s);
+int dot_f64_launch(int64_t len, const double* a, const double* b, double* out, double* partial,
+                   int nblocks, hipStream_t s);
+
+}  // namespace nmf
+
+// ---- device helpers -----------------------------------------------------------
+
+// Orders a wavefront's own LDS writes before its subsequent LDS reads by other
+// lanes of the same wavefront (no workgroup barrier needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}

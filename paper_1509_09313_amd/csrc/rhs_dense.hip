@@ -1,0 +1,347 @@
+// Dense right-hand sides of the two ANLS updates (Algorithm 1):
+//   side W:  R (m x k) = A (m x n) * Ht (n x k)        = A H^T
+//   side H:  R (n x k) = A^T (n x m) * W (m x k)       = (W^T A)^T
+// These are the "MM" local products of the paper (Algorithm 3's V_ij and
+// Y_ij at p = 1).  k <= 64 is the short dimension; A is streamed once.
+//
+// FP32 path: v_mfma_f32_32x32x2_f32.  Output tiles are 32 (k) x 32 (rows of
+// A or columns of A).  The contraction index inside one K-chunk is permuted
+// freely (A and B operands use the same permutation) so that every lane's
+// operand comes from one 16-byte load.
+//   side W stages 128 x 32 tiles of A in LDS (rows of A are contracted
+//     along their contiguous dimension, so lanes need different rows);
+//   side H needs no LDS: lane (j, h) loads A[r + h][c0 + 4j .. +3] with one
+//     16-byte load (a 512-byte contiguous segment per half-wave) and feeds
+//     four MFMAs, one per component; the rows of A are split into S ranges
+//     whose FP32 partials are summed in FP64 in a fixed order.
+// BF16X3 path: see rhs_bf16.hip.
+#include "nmf_common.h"
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+namespace {
+
+__device__ __forceinline__ v16f mfma32(float a, float b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- side W --
+constexpr int kWTM = 128;  // rows of A per block (4 waves x 32)
+constexpr int kWTK = 32;   // contraction chunk (columns of A)
+constexpr int kWPitch = kWTK + 4;
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(256) void k_rhs_w_f32(int64_t m, int64_t n, int k, const float* __restrict__ A,
+                                                   int64_t lda, const float* __restrict__ Y, int64_t ldy,
+                                                   float* __restrict__ R, int64_t ldr) {
+  constexpr int KP = 32 * NT;
+  constexpr int YP = KP + 4;
+  constexpr int YPER = KP * kWTK / 256;  // Y values staged per thread
+  __shared__ __align__(16) float As[kWTM * kWPitch];
+  __shared__ __align__(16) float Ys[kWTK * YP];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int j = lane & 31, h = lane >> 5;
+  const int64_t row0 = (int64_t)blockIdx.x * kWTM;
+
+  v16f acc[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) acc[tt] = v16f{};
+
+  float4 ra[4];
+  float ry[YPER];
+  auto load = [&](int64_t n0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int q = t + 256 * s;
+      const int rr = q >> 3, c4 = q & 7;
+      const int64_t r = row0 + rr, c = n0 + 4 * c4;
+      const float* src = A + r * lda + c;
+      if (VEC && r < m && c + 3 < n) {
+        ra[s] = *reinterpret_cast<const float4*>(src);
+      } else {
+        ra[s].x = (r < m && c + 0 < n) ? src[0] : 0.0f;
+        ra[s].y = (r < m && c + 1 < n) ? src[1] : 0.0f;
+        ra[s].z = (r < m && c + 2 < n) ? src[2] : 0.0f;
+        ra[s].w = (r < m && c + 3 < n) ? src[3] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < YPER; ++s) {
+      const int e = t + 256 * s;
+      const int kk = e / KP, cc = e - kk * KP;
+      ry[s] = (n0 + kk < n && cc < k) ? Y[(n0 + kk) * ldy + cc] : 0.0f;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int q = t + 256 * s;
+      const int rr = q >> 3, c4 = q & 7;
+      *reinterpret_cast<float4*>(&As[rr * kWPitch + 4 * c4]) = ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < YPER; ++s) {
+      const int e = t + 256 * s;
+      const int kk = e / KP, cc = e - kk * KP;
+      Ys[kk * YP + cc] = ry[s];
+    }
+  };
+
+  load(0);
+  for (int64_t n0 = 0; n0 < n; n0 += kWTK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (n0 + kWTK < n) load(n0 + kWTK);
+#pragma unroll
+    for (int sg = 0; sg < kWTK / 8; ++sg) {
+      const float4 a4 = *reinterpret_cast<const float4*>(&As[(32 * w + j) * kWPitch + 8 * sg + 4 * h]);
+      const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = 8 * sg + 4 * h + q;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) acc[tt] = mfma32(Ys[kk * YP + 32 * tt + j], av[q], acc[tt]);
+      }
+    }
+  }
+  // D_tt[i][j] = R[row0 + 32w + j][32 tt + i]; lane holds i = (v&3) + 8(v>>2) + 4h
+  const int64_t r = row0 + 32 * w + j;
+  if (r < m) {
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int c = 32 * tt + (v & 3) + 8 * (v >> 2) + 4 * h;
+        if (c < k) R[r * ldr + c] = acc[tt][v];
+      }
+  }
+}
+
+// ---------------------------------------------------------------- side H --
+constexpr int kHCols = 128;  // columns of A per wave
+constexpr int kHUnroll = 8;  // row pairs in flight per lane
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(64) void k_rhs_h_f32(int64_t m, int64_t n, int k, const float* __restrict__ A,
+                                                  int64_t lda, const float* __restrict__ Y, int64_t ldy,
+                                                  float* __restrict__ P, int64_t ldp, int64_t rows_per_split,
+                                                  int64_t split_stride) {
+  const int lane = threadIdx.x;
+  const int j = lane & 31, h = lane >> 5;
+  const int64_t c0 = (int64_t)blockIdx.x * kHCols;
+  const int64_t col = c0 + 4 * j;
+  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+
+  v16f acc[4][NT];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[q][tt] = v16f{};
+
+  for (int64_t r = r_begin; r < r_end; r += 2 * kHUnroll) {
+    float4 a[kHUnroll];
+    float wv[kHUnroll][NT];
+#pragma unroll
+    for (int u = 0; u < kHUnroll; ++u) {
+      const int64_t rr = r + 2 * u + h;
+      const bool rok = rr < r_end;
+      const float* src = A + rr * lda + col;
+      if (VEC && rok && col + 3 < n) {
+        a[u] = *reinterpret_cast<const float4*>(src);
+      } else {
+        a[u].x = (rok && col + 0 < n) ? src[0] : 0.0f;
+        a[u].y = (rok && col + 1 < n) ? src[1] : 0.0f;
+        a[u].z = (rok && col + 2 < n) ? src[2] : 0.0f;
+        a[u].w = (rok && col + 3 < n) ? src[3] : 0.0f;
+      }
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) {
+        const int c = 32 * tt + j;
+        wv[u][tt] = (rok && c < k) ? Y[rr * ldy + c] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kHUnroll; ++u) {
+      const float av[4] = {a[u].x, a[u].y, a[u].z, a[u].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) acc[q][tt] = mfma32(wv[u][tt], av[q], acc[q][tt]);
+    }
+  }
+  // D_{q,tt}[i][j] = R[c0 + 4j + q][32 tt + i]
+  float* out = P + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t row = col + q;
+    if (row >= n) continue;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int c = 32 * tt + (v & 3) + 8 * (v >> 2) + 4 * h;
+        if (c < k) out[row * ldp + c] = acc[q][tt][v];
+      }
+  }
+}
+
+// R[row][c] = sum_s P[s][row][c], summed in FP64 in split order.
+__global__ void k_split_reduce(int64_t n, int k, int S, const float* __restrict__ P, int64_t split_stride,
+                               float* __restrict__ R, int64_t ldr) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t row = e / k;
+  const int c = (int)(e - row * k);
+  double s = 0.0;
+  for (int sp = 0; sp < S; ++sp) s += (double)P[sp * split_stride + e];
+  R[row * ldr + c] = (float)s;
+}
+
+struct HSplit {
+  int64_t colgroups;
+  int S;
+  int64_t rows_per_split;
+};
+
+HSplit h_split(int64_t m, int64_t n) {
+  HSplit s;
+  s.colgroups = nmf::cdiv(n, kHCols);
+  const int64_t target_waves = 3072;
+  int64_t S = nmf::cdiv(target_waves, s.colgroups);
+  const int64_t max_s = m / 512 > 1 ? m / 512 : 1;
+  if (S > max_s) S = max_s;
+  if (S > 65535) S = 65535;
+  if (S < 1) S = 1;
+  int64_t rps = nmf::cdiv(m, S);
+  rps = (rps + 2 * kHUnroll - 1) / (2 * kHUnroll) * (2 * kHUnroll);
+  s.S = (int)nmf::cdiv(m, rps > 0 ? rps : 1);
+  if (s.S < 1) s.S = 1;
+  s.rows_per_split = rps > 0 ? rps : 2 * kHUnroll;
+  return s;
+}
+
+template <int NT>
+int launch_w_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const float* Y, int64_t ldy,
+                 float* R, int64_t ldr, hipStream_t s) {
+  const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+  const dim3 grid((unsigned)nmf::cdiv(m, kWTM));
+  if (vec)
+    hipLaunchKernelGGL((k_rhs_w_f32<NT, true>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
+  else
+    hipLaunchKernelGGL((k_rhs_w_f32<NT, false>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
+  return nmf::launch_status("rhs side W (fp32)");
+}
+
+template <int NT>
+int launch_h_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const float* Y, int64_t ldy,
+                 float* R, int64_t ldr, float* partial, hipStream_t s) {
+  const HSplit sp = h_split(m, n);
+  const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+  float* P = sp.S > 1 ? partial : R;
+  const int64_t ldp = sp.S > 1 ? k : ldr;
+  const int64_t stride = sp.S > 1 ? n * k : 0;
+  const dim3 grid((unsigned)sp.colgroups, (unsigned)sp.S);
+  if (vec)
+    hipLaunchKernelGGL((k_rhs_h_f32<NT, true>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
+                       sp.rows_per_split, stride);
+  else
+    hipLaunchKernelGGL((k_rhs_h_f32<NT, false>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
+                       sp.rows_per_split, stride);
+  NMF_TRY(nmf::launch_status("rhs side H (fp32)"));
+  if (sp.S > 1) {
+    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)nmf::cdiv(n * k, 256)), dim3(256), 0, s, n, k, sp.S,
+                       partial, stride, R, ldr);
+    NMF_TRY(nmf::launch_status("rhs side H reduce"));
+  }
+  return NMF_OK;
+}
+
+}  // namespace
+
+// BF16X3 entry points (rhs_bf16.hip)
+namespace nmf {
+int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch);
+int bf16x3_launch(int side, int64_t m, int64_t n, int k, const uint16_t* B_hi, const uint16_t* B_lo,
+                  int64_t ldb, const float* Y, int64_t ldy, float* R, int64_t ldr, void* scratch,
+                  hipStream_t s);
+}
+
+namespace nmf {
+
+int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, void** scratch) {
+  *scratch = nullptr;
+  if (prec == NMF_BF16X3) return bf16x3_plan(side, m, n, k, c, scratch);
+  if (side == NMF_SIDE_H) {
+    const HSplit sp = h_split(m, n);
+    if (sp.S > 1) *scratch = c.take<float>((size_t)sp.S * n * k);
+  }
+  return NMF_OK;
+}
+
+int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const uint16_t* B_hi,
+                     const uint16_t* B_lo, int64_t ldb, const float* Y, int64_t ldy, float* R, int64_t ldr,
+                     int prec, void* scratch, hipStream_t s) {
+  if (prec == NMF_BF16X3) return bf16x3_launch(side, m, n, k, B_hi, B_lo, ldb, Y, ldy, R, ldr, scratch, s);
+  if (side == NMF_SIDE_W) {
+    if (m == 0) return NMF_OK;
+    return k <= 32 ? launch_w_f32<1>(m, n, k, A, lda, Y, ldy, R, ldr, s)
+                   : launch_w_f32<2>(m, n, k, A, lda, Y, ldy, R, ldr, s);
+  }
+  if (n == 0) return NMF_OK;
+  return k <= 32 ? launch_h_f32<1>(m, n, k, A, lda, Y, ldy, R, ldr, static_cast<float*>(scratch), s)
+                 : launch_h_f32<2>(m, n, k, A, lda, Y, ldy, R, ldr, static_cast<float*>(scratch), s);
+}
+
+}  // namespace nmf
+
+static int check_rhs_args(int side, int64_t m, int64_t n, int k, int prec, const float* A, int64_t lda,
+                          const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y,
+                          int64_t ldy, const float* R, int64_t ldr) {
+  if (side != NMF_SIDE_W && side != NMF_SIDE_H) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: bad side %d", side);
+  if (prec != NMF_F32 && prec != NMF_BF16X3) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: bad prec %d", prec);
+  if (!nmf::valid_k(k)) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: k=%d outside [1,64]", k);
+  if (m < 0 || n < 0) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: negative size");
+  if (ldy < k || ldr < k) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: ldy/ldr < k");
+  const int64_t rows_out = side == NMF_SIDE_W ? m : n;
+  if (rows_out > 0 && !R) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: R is null");
+  if (m > 0 && n > 0 && !Y) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: Y is null");
+  if (prec == NMF_F32) {
+    if (lda < n) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: lda < n");
+    if (m > 0 && n > 0 && !A) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: A is null");
+  } else {
+    const int64_t contracted = side == NMF_SIDE_W ? n : m;
+    if (ldb < contracted) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: ldb too small for the BF16 planes");
+    if (m > 0 && n > 0 && (!B_hi || !B_lo)) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: BF16 planes are null");
+  }
+  return NMF_OK;
+}
+
+extern "C" int nmf_rhs_dense_workspace_bytes(int side, int64_t m, int64_t n, int k, int prec, size_t* bytes) {
+  if (!bytes) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_workspace_bytes: bytes is null");
+  if (side != NMF_SIDE_W && side != NMF_SIDE_H) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_workspace_bytes: bad side");
+  if (prec != NMF_F32 && prec != NMF_BF16X3) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_workspace_bytes: bad prec");
+  if (!nmf::valid_k(k) || m < 0 || n < 0) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_workspace_bytes: bad sizes");
+  nmf::Carver c(nullptr, 0);
+  void* scratch;
+  NMF_TRY(nmf::rhs_dense_plan(side, m, n, k, prec, c, &scratch));
+  *bytes = c.off;
+  return NMF_OK;
+}
+
+extern "C" int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda,
+                             const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y, int64_t ldy,
+                             float* R, int64_t ldr, int prec, void* ws, size_t ws_bytes, void* stream) {
+  NMF_TRY(check_rhs_args(side, m, n, k, prec, A, lda, B_hi, B_lo, ldb, Y, ldy, R, ldr));
+  nmf::Carver c(ws, ws_bytes);
+  void* scratch;
+  NMF_TRY(nmf::rhs_dense_plan(side, m, n, k, prec, c, &scratch));
+  if (c.off > 0 && (!ws || !c.fits()))
+    return nmf::fail(NMF_EWORKSPACE, "nmf_rhs_dense: workspace %zu < %zu bytes", ws_bytes, c.off);
+  // an empty contraction gives R = 0
+  if (n == 0 && side == NMF_SIDE_W) return nmf::zero_f32(R, m, k, ldr, nmf::as_stream(stream));
+  if (m == 0 && side == NMF_SIDE_H) return nmf::zero_f32(R, n, k, ldr, nmf::as_stream(stream));
+  return nmf::rhs_dense_launch(side, m, n, k, A, lda, B_hi, B_lo, ldb, Y, ldy, R, ldr, prec, scratch,
+                               nmf::as_stream(stream));
+}

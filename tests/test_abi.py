@@ -1,0 +1,86 @@
+"""The C-ABI boundary on the host: libnmf.so loads, exports every function
+include/libnmf.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libnmf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(nmf_\w+|nnls_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1509_09313_amd import binding as libnmf
+    if not os.path.exists(libnmf.LIB_PATH):
+        from paper_1509_09313_amd import build
+        build.build()
+    return libnmf
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("nmf_gram", "nmf_rhs_dense", "nmf_rhs_csr", "nnls_bpp_batched", "nmf_anls_iter",
+                     "nmf_objective"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    lib = L.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_validation_without_gpu(L):
+    lib = L.lib()
+    G = ctypes.c_void_p(16)
+    # k outside [1, 64]
+    assert lib.nmf_gram(10, 0, G, 1, G, G, 1 << 20, None) == L.NMF_EINVAL
+    assert b"k=0" in lib.nmf_last_error()
+    assert lib.nmf_gram(10, 65, G, 65, G, G, 1 << 20, None) == L.NMF_EINVAL
+    # ldx < k
+    assert lib.nmf_gram(10, 8, G, 4, G, G, 1 << 20, None) == L.NMF_EINVAL
+    # workspace too small
+    nb = ctypes.c_size_t(0)
+    assert lib.nmf_gram_workspace_bytes(1000, 8, ctypes.byref(nb)) == L.NMF_OK and nb.value > 0
+    assert lib.nmf_gram(1000, 8, G, 8, G, G, nb.value - 1, None) == L.NMF_EWORKSPACE
+    # BPP: bad caps and sizes
+    assert lib.nnls_bpp_batched(8, 10, G, G, 8, G, 8, None, None, None, None, 0, 8, None, None) == L.NMF_EINVAL
+    assert lib.nnls_bpp_batched(8, 10, G, G, 4, G, 8, None, None, None, None, 10, 8, None, None) == L.NMF_EINVAL
+    assert lib.nnls_bpp_batched(8, 10, None, G, 8, G, 8, None, None, None, None, 10, 8, None, None) == L.NMF_EINVAL
+    # RHS: bad side, bad prec, lda < n, missing BF16 planes
+    z = ctypes.c_void_p(0)
+    assert lib.nmf_rhs_dense(7, 4, 4, 2, G, 4, z, z, 4, G, 2, G, 2, 0, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_rhs_dense(0, 4, 4, 2, G, 4, z, z, 4, G, 2, G, 2, 9, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_rhs_dense(0, 4, 4, 2, G, 3, z, z, 4, G, 2, G, 2, 0, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_rhs_dense(0, 4, 4, 2, z, 4, z, z, 4, G, 2, G, 2, 1, G, 1 << 20, None) == L.NMF_EINVAL
+    # CSR: ld < k
+    assert lib.nmf_rhs_csr(4, 4, 8, G, G, G, G, 4, G, 8, None) == L.NMF_EINVAL
+    # objective and ANLS: null matrix / bad opts
+    assert lib.nmf_objective(None, 4, G, G, 0, None, None, None, G, G, 1 << 20, None) == L.NMF_EINVAL
+    M = L.nmf_matrix()
+    M.kind, M.m, M.n, M.A, M.lda = L.NMF_DENSE, 10, 8, 16, 8
+    o = L.make_opts(max_rounds=0)
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
+    o = L.make_opts(prec=L.NMF_BF16X3)
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
+    o = L.make_opts(warm=L.NMF_WARM_LEARNED)
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
+    o = L.make_opts()
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_OK
+    assert nb.value > 0
+
+
+def test_struct_layouts_match_header(L):
+    # sizes of the C structs as the library sees them are fixed by the header;
+    # the Python mirror must agree field for field.
+    assert ctypes.sizeof(L.nmf_iter_stats) == 8 * (2 + 2 * L.NMF_BPP_COUNTERS + 2)
+    assert L.nmf_matrix.fro2.offset == ctypes.sizeof(L.nmf_matrix) - 8

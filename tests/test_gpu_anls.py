@@ -1,0 +1,127 @@
+"""ANLS-BPP trajectories on the GPU (through nmf_anls_iter) against the FP64
+CPU oracle from the same seeded inputs: the relative objective after every
+half-step must agree within 1e-5 (absolute, in units of ||A - WH||_F / ||A||_F),
+the GPU objective must be non-increasing like the oracle's, and the supports
+of the final factors are compared (agreement fraction reported)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from nmf_inputs import configs as C
+from nmf_inputs import device as gen
+from paper_1509_09313_amd import binding as L
+
+pytestmark = pytest.mark.gpu
+
+RTOL_OBJ = 1e-5
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_gpu(M, k, W0, H0, iters, **kw):
+    W = cuda(W0)
+    Ht = cuda(H0)
+    stats = L.new_stats(iters)
+    L.nmf_anls_iter(M, k, W, Ht, iters, L.make_opts(**kw), stats)
+    st = L.decode_stats(stats)
+    return W.cpu().numpy(), Ht.cpu().numpy(), st
+
+
+def support_agreement(a, b):
+    return float(np.mean((a > 0) == (b > 0)))
+
+
+def check_traj(st, ref, label):
+    rh = np.array([s["r_half"] for s in st])
+    rf = np.array([s["r_full"] for s in st])
+    dh = np.max(np.abs(rh - ref["r_half"]))
+    df = np.max(np.abs(rf - ref["r_full"]))
+    print(f"{label}: final r gpu={rf[-1]:.9f} oracle={ref['r_full'][-1]:.9f} max|dr| half={dh:.2e} full={df:.2e}")
+    assert dh <= RTOL_OBJ and df <= RTOL_OBJ
+    assert all(s["capped"] == 0 for s in st)
+    # the trace-form objective is non-increasing up to its cancellation floor
+    seq = np.ravel(np.column_stack([rh, rf]))
+    assert np.all(np.diff(seq) <= 1e-6)
+
+
+def test_config1_trajectory():
+    w = C.WORKLOADS["c1"]
+    A = C.config1_matrix(w.m, w.n, w.rank)
+    W0, H0 = C.init_w(w.seed, w.m, w.k), C.init_ht(w.seed, w.n, w.k)
+    ref = oracle.anls(w.k, W0, H0, w.iters, dense=A)
+    M = L.Matrix(dense=cuda(A))
+    W, Ht, st = run_gpu(M, w.k, W0, H0, w.iters)
+    check_traj(st, ref, "config1")
+    obj = L.nmf_objective(M, cuda(W), cuda(Ht)).cpu().numpy()
+    assert abs(obj[0] - ref["r_full"][-1]) <= RTOL_OBJ
+    assert support_agreement(W, ref["W"]) >= 0.999
+    assert support_agreement(Ht, ref["Ht"]) >= 0.999
+    # BPP round counts per half-step match the oracle's
+    assert [s["bpp_w"][0] for s in st] == list(ref["rounds_w"])
+
+
+def test_config1_warm_prev_matches_cold():
+    w = C.WORKLOADS["c1"]
+    A = C.config1_matrix(w.m, w.n, w.rank)
+    W0, H0 = C.init_w(w.seed, w.m, w.k), C.init_ht(w.seed, w.n, w.k)
+    ref = oracle.anls(w.k, W0, H0, w.iters, dense=A)
+    M = L.Matrix(dense=cuda(A))
+    W, Ht, st = run_gpu(M, w.k, W0, H0, w.iters, warm=L.NMF_WARM_PREV, warm_cap=50)
+    check_traj(st, ref, "config1 warm-prev")
+    assert sum(s["bpp_w"][0] for s in st[1:]) < ref["rounds_w"][1:].sum()
+
+
+def test_sparse_small_trajectory():
+    w = C.WORKLOADS["c3s"]
+    rp, ci, va = C.sparse_csr(w.seed, w.m, w.n, w.density, inst=w.inst)
+    rpt, cit, vat = C.csr_transpose(w.m, w.n, rp, ci, va)
+    W0, H0 = C.init_w(w.seed, w.m, w.k, inst=w.inst), C.init_ht(w.seed, w.n, w.k, inst=w.inst)
+    ref = oracle.anls(w.k, W0, H0, w.iters, csr=(rp, ci, va), csr_t=(rpt, cit, vat), shape=(w.m, w.n))
+    M = L.Matrix(csr=(cuda(rp), cuda(ci), cuda(va)), csr_t=(cuda(rpt), cuda(cit), cuda(vat)), shape=(w.m, w.n))
+    W, Ht, st = run_gpu(M, w.k, W0, H0, w.iters)
+    check_traj(st, ref, "sparse 2000x1500")
+    obj = L.nmf_objective(M, cuda(W), cuda(Ht)).cpu().numpy()
+    assert abs(obj[0] - ref["r_full"][-1]) <= RTOL_OBJ
+
+
+def test_dense_planted_scaled_trajectory():
+    w = C.WORKLOADS["c2s"]
+    iters = 10
+    A = C.dense_rows(w, np.arange(w.m))
+    W0, H0 = C.init_w(w.seed, w.m, w.k), C.init_ht(w.seed, w.n, w.k)
+    ref = oracle.anls(w.k, W0, H0, iters, dense=A)
+    M = L.Matrix(dense=cuda(A))
+    W, Ht, st = run_gpu(M, w.k, W0, H0, iters)
+    check_traj(st, ref, "planted 1728x1152 k=50")
+    print("support agreement W", support_agreement(W, ref["W"]), "H", support_agreement(Ht, ref["Ht"]))
+
+
+def test_video_rows_trajectory():
+    """The first 8000 rows of the video-like matrix (k = 30), built by the
+    device generator (bit-identical to the host recipe, see the generator test)."""
+    seed, m, n, k, iters = C.seed_for(5), 8000, 2400, 30, 5
+    Ad = gen.video(seed, m, n)
+    A = Ad.cpu().numpy()
+    W0, H0 = C.init_w(seed, m, k), C.init_ht(seed, n, k)
+    ref = oracle.anls(k, W0, H0, iters, dense=A)
+    M = L.Matrix(dense=Ad)
+    W, Ht, st = run_gpu(M, k, W0, H0, iters)
+    check_traj(st, ref, "video 8000x2400 k=30")
+    print("support agreement W", support_agreement(W, ref["W"]), "H", support_agreement(Ht, ref["Ht"]))
+
+
+def test_device_generators_bit_identical():
+    seed = C.seed_for(5)
+    Ad = gen.video(seed, 3000, 2400).cpu().numpy()
+    rows = np.array([0, 1, 17, 999, 2999])
+    assert np.array_equal(Ad[rows], C.video_rows(seed, 2400, rows))
+    seed2 = C.seed_for(2)
+    Pd = gen.planted(seed2, 700, 513, 50).cpu().numpy()
+    rows = np.array([0, 5, 699])
+    assert np.array_equal(Pd[rows], C.planted_rows(seed2, 513, 50, rows))
+    Wd, Htd = gen.init_factors(seed, 3000, 2400, 30)
+    assert np.array_equal(Wd.cpu().numpy(), C.init_w(seed, 3000, 30))
+    assert np.array_equal(Htd.cpu().numpy(), C.init_ht(seed, 2400, 30))
