@@ -133,6 +133,43 @@ int nnls_bpp_batched(int k, int64_t batch, const double* G, const float* R, int6
                      int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds,
                      uint8_t* status, int max_rounds, int warm_cap, uint64_t* counters, void* stream);
 
+/* ---- learned warm start ---------------------------------------------------
+ * A network predicts each problem's starting passive set for BPP (Section
+ * "Block Principal Pivoting": BPP searches for this set; any start is
+ * verified by the KKT test of Eq. KKT and a start that does not converge in
+ * warm_cap rounds restarts cold).  Features of a problem (G, f):
+ *   phi = [ s / ||s||_2 , diag(G) / mean(diag(G)) ]  (2k),  s_i = f_i / sqrt(G_ii)
+ * (s_i = 0 for pinned indices); network 2k -> 128 -> 128 -> k with ReLU,
+ * start set { i : logit_i > 0 } minus pinned indices.  Parameters: one FP32
+ * device vector, W1[2k][128], b1[128], W2[128][128], b2[128], W3[128][k],
+ * b3[k] (input-major); nmf_mlp_param_count(k) gives its length. */
+int nmf_mlp_param_count(int k);
+
+/* phi (batch x 2k FP32, device) of the rows of R (ldr >= k) against G. */
+int nmf_features(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* phi, void* stream);
+
+/* Start sets for every row of R: features and the three layers fused on BF16
+ * MFMA (FP32 accumulation), written to mask_out (device uint64 per row). */
+int nmf_mlp_predict(int k, int64_t batch, const double* G, const float* R, int64_t ldr, const float* params,
+                    uint64_t* mask_out, void* stream);
+
+/* Training in FP32 on (phi, final passive set) samples (device, nsamples of
+ * each) by Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * mean binary cross-entropy.  Step t (t = step0 .. step0+steps-1) uses the
+ * samples order[(t - step0) * batch + i], i < batch, when `order` (device
+ * int64, steps * batch entries in [0, nsamples)) is given, else the fixed
+ * draw ((t * 1000003 + i + 1) * 0x9E3779B97F4A7C15 >> 11) mod nsamples; the
+ * bias correction uses t + 1.  params, adam_m, adam_v are updated in place.
+ * loss_out (optional, device FP64): mean loss of the last step's batch.
+ * nmf_mlp_grad: the gradient (FP32, param-count entries) and mean loss of the
+ * first `batch` samples, for checking. */
+int nmf_mlp_train_workspace_bytes(int k, int batch, size_t* bytes);
+int nmf_mlp_grad(int k, int batch, const float* params, const float* phi, const uint64_t* masks, float* grad_out,
+                 double* loss_out, void* ws, size_t ws_bytes, void* stream);
+int nmf_mlp_train(int k, float* params, float* adam_m, float* adam_v, const float* phi, const uint64_t* masks,
+                  int64_t nsamples, const int64_t* order, int steps, int batch, float lr, int64_t step0,
+                  double* loss_out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- the data matrix ------------------------------------------------------- */
 typedef struct nmf_matrix {
   int kind;                 /* NMF_DENSE or NMF_CSR */

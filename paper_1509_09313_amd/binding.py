@@ -92,6 +92,13 @@ def lib():
             "nmf_objective": ([M, ci, vp, vp, ci, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ci),
             "nmf_anls_workspace_bytes": ([M, ci, O, sz], ci),
             "nmf_anls_iter": ([M, ci, vp, vp, ci, O, vp, vp, ctypes.c_size_t, vp], ci),
+            "nmf_mlp_param_count": ([ci], ci),
+            "nmf_features": ([ci, i64, vp, vp, i64, vp, vp], ci),
+            "nmf_mlp_predict": ([ci, i64, vp, vp, i64, vp, vp, vp], ci),
+            "nmf_mlp_train_workspace_bytes": ([ci, ci, sz], ci),
+            "nmf_mlp_grad": ([ci, ci, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ci),
+            "nmf_mlp_train": ([ci, vp, vp, vp, vp, vp, i64, vp, ci, ci, ctypes.c_float, i64, vp, vp,
+                               ctypes.c_size_t, vp], ci),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -317,3 +324,62 @@ def nmf_anls_iter(M: Matrix, k, W, Ht, iters, opts=None, stats=None):
     runner = Anls(M, k, opts)
     runner.run(W, Ht, iters, stats)
     return runner
+
+
+# ---------------------------------------------------------------- network --
+def nmf_mlp_param_count(k):
+    return lib().nmf_mlp_param_count(k)
+
+
+def nmf_features(G, R):
+    _dev(G, torch.float64, "G")
+    _dev(R, torch.float32, "R")
+    batch, k = R.shape
+    phi = torch.empty((batch, 2 * k), dtype=torch.float32, device="cuda")
+    _check(lib().nmf_features(k, batch, _ptr(G), _ptr(R), _ld(R), _ptr(phi), _stream()))
+    return phi
+
+
+def nmf_mlp_predict(G, R, params, mask_out=None):
+    _dev(G, torch.float64, "G")
+    _dev(R, torch.float32, "R")
+    batch, k = R.shape
+    if mask_out is None:
+        mask_out = torch.empty(batch, dtype=torch.int64, device="cuda")
+    _check(lib().nmf_mlp_predict(k, batch, _ptr(G), _ptr(R), _ld(R), _ptr(params), _ptr(mask_out), _stream()))
+    return mask_out
+
+
+def nmf_mlp_grad(k, params, phi, masks, batch=None):
+    batch = phi.shape[0] if batch is None else batch
+    nb = ctypes.c_size_t(0)
+    _check(lib().nmf_mlp_train_workspace_bytes(k, batch, ctypes.byref(nb)))
+    ws = _ws(nb.value)
+    grad = torch.empty(nmf_mlp_param_count(k), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(lib().nmf_mlp_grad(k, batch, _ptr(params), _ptr(phi), _ptr(masks), _ptr(grad), _ptr(loss), _ptr(ws),
+                              nb.value, _stream()))
+    return grad, loss
+
+
+class MlpTrainer:
+    """Parameters and Adam moments of one network, trained by nmf_mlp_train."""
+
+    def __init__(self, k, params, batch=1024, lr=1e-3):
+        self.k, self.batch, self.lr = k, batch, lr
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = 0
+        nb = ctypes.c_size_t(0)
+        _check(lib().nmf_mlp_train_workspace_bytes(k, batch, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = _ws(nb.value)
+        self.loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def train(self, phi, masks, nsamples, steps, order=None):
+        _check(lib().nmf_mlp_train(self.k, _ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(phi), _ptr(masks),
+                                   int(nsamples), _ptr(order), int(steps), self.batch, ctypes.c_float(self.lr),
+                                   self.step, _ptr(self.loss), _ptr(self.ws), self.ws_bytes, _stream()))
+        self.step += steps
+        return self.loss

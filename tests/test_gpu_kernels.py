@@ -246,3 +246,41 @@ def test_objective_csr():
     assert abs(out[2] - fa) <= 1e-12 * fa
     assert abs(out[1] - fr) <= 1e-9 * (fa + abs(fr))
     assert abs(M.fro2.item() - fa) <= 1e-12 * fa
+
+
+# ----------------------------------------------------------- BF16x3 RHS ----
+from oracle import split as osplit  # noqa: E402
+
+
+@pytest.mark.parametrize("m,n,k,pad", [(200, 150, 5, 0), (257, 131, 30, 0), (129, 1000, 50, 1), (33, 4097, 64, 0),
+                                       (1000, 999, 33, 3), (70000, 300, 30, 0), (20000, 2400, 30, 8)])
+def test_rhs_dense_bf16x3(m, n, k, pad):
+    """Bound: each of the 3L BF16 products is exact in FP32 and the chain is
+    accumulated in FP32, so |R - oracle| <= 3 L 2^-24 (|A||Y|) (1 + small)."""
+    rng = np.random.default_rng(3 * m + n + k)
+    A = rng.uniform(0.0, 1.0, (m, n)).astype(np.float32)
+    Ht = rng.uniform(0.0, 1.0, (n, k)).astype(np.float32)
+    W = rng.uniform(0.0, 1.0, (m, k)).astype(np.float32)
+    Ad = padded(A, pad)
+    hi, lo = L.nmf_split_bf16(Ad)
+    hit, lot = L.nmf_split_bf16(Ad, transpose=True)
+    hb, lb = osplit.split_bits(A)
+    assert np.array_equal(hi.cpu().numpy().view(np.uint16), hb)
+    assert np.array_equal(lo.cpu().numpy().view(np.uint16), lb)
+    assert np.array_equal(hit.cpu().numpy().view(np.uint16), hb.T)
+    assert np.array_equal(lot.cpu().numpy().view(np.uint16), lb.T)
+    A64 = np.abs(A.astype(np.float64))
+    Rw = L.nmf_rhs_dense(L.NMF_SIDE_W, None, cuda(Ht), prec=L.NMF_BF16X3, B_hi=hi, B_lo=lo, m=m, n=n)
+    Rwo = osplit.rhs_w(A, Ht)
+    bw = 1.01 * 3 * n * U32 * (A64 @ np.abs(Ht.astype(np.float64)))
+    err = np.abs(Rw.cpu().numpy().astype(np.float64) - Rwo)
+    assert np.all(err <= bw), np.max(err / bw)
+    Rh = L.nmf_rhs_dense(L.NMF_SIDE_H, None, cuda(W), prec=L.NMF_BF16X3, B_hi=hit, B_lo=lot, m=m, n=n)
+    Rho = osplit.rhs_h(A, W)
+    bh = 1.01 * 3 * (m + 1) * U32 * (A64.T @ np.abs(W.astype(np.float64)))
+    err = np.abs(Rh.cpu().numpy().astype(np.float64) - Rho)
+    assert np.all(err <= bh), np.max(err / bh)
+    # and against the exact product: the dropped lo*lo term and the split error
+    exact = A.astype(np.float64) @ Ht.astype(np.float64)
+    bex = (3 * 2.0 ** -16 + 3.03 * n * U32) * (A64 @ np.abs(Ht.astype(np.float64)))
+    assert np.all(np.abs(Rw.cpu().numpy() - exact) <= bex)

@@ -1,0 +1,144 @@
+"""The warm-start network on the GPU against its FP64 oracle (oracle/mlp.py):
+features, the loss gradient (checked in turn against finite differences in
+the CPU tests), Adam steps on an explicit sample order, the fused BF16
+inference, and the learned warm start inside the ANLS driver."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp as omlp
+from nmf_inputs import configs as C
+from paper_1509_09313_amd import binding as L
+
+pytestmark = pytest.mark.gpu
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def problems(k, batch, seed):
+    rng = np.random.default_rng(seed)
+    Cm = rng.uniform(0.0, 1.0, (3 * k, k))
+    Cm[:, k // 2] *= 1e-9 if k > 2 else 1.0      # one (nearly) pinned index
+    G = Cm.T @ Cm
+    R = (rng.standard_normal((batch, 3 * k)) @ Cm + 0.3 * Cm.sum(0)).astype(np.float32)
+    return G, R
+
+
+@pytest.mark.parametrize("k", [5, 30, 50])
+def test_features(k):
+    G, R = problems(k, 777, k)
+    phi = L.nmf_features(cuda(G), cuda(R)).cpu().numpy()
+    ref = omlp.features(G, R.astype(np.float64))
+    np.testing.assert_allclose(phi, ref, rtol=2e-6, atol=2e-7)
+
+
+def train_inputs(k, n, seed):
+    G, R = problems(k, n, seed)
+    phi = omlp.features(G, R.astype(np.float64)).astype(np.float32)
+    _, masks, _, _ = oracle.bpp_batched(G, R.astype(np.float64))
+    p = C.mlp_init(k, 1234 + k)
+    return phi, masks, p
+
+
+@pytest.mark.parametrize("k,batch", [(5, 64), (30, 1000), (50, 333)])
+def test_gradient_matches_oracle(k, batch):
+    phi, masks, p = train_inputs(k, batch, 7 + k)
+    g, loss = L.nmf_mlp_grad(k, cuda(p), cuda(phi), cuda(masks.view(np.int64)))
+    g = g.cpu().numpy().astype(np.float64)
+    z, cache = omlp.forward(p.astype(np.float64), phi.astype(np.float64), k)
+    t = omlp.targets(masks, k)
+    go = omlp.backward(p.astype(np.float64), cache, z, t, k)
+    assert abs(loss.item() - omlp.loss(z, t)) <= 1e-5 * omlp.loss(z, t)
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+    assert np.all(np.abs(g - go) <= 1e-4 * np.abs(go).max() + 1e-3 * np.abs(go))
+
+
+def test_adam_steps_match_oracle():
+    k, n, batch, steps = 30, 4000, 256, 5
+    phi, masks, p = train_inputs(k, n, 99)
+    order = np.random.default_rng(5).integers(0, n, steps * batch).astype(np.int64)
+    tr = L.MlpTrainer(k, cuda(p.copy()), batch=batch, lr=1e-3)
+    tr.train(cuda(phi), cuda(masks.view(np.int64)), n, steps, order=cuda(order))
+    pg = tr.params.cpu().numpy().astype(np.float64)
+    po = p.astype(np.float64)
+    mo = np.zeros_like(po)
+    vo = np.zeros_like(po)
+    t_all = omlp.targets(masks, k)
+    for s in range(steps):
+        idx = order[s * batch:(s + 1) * batch]
+        z, cache = omlp.forward(po, phi[idx].astype(np.float64), k)
+        g = omlp.backward(po, cache, z, t_all[idx], k)
+        po, mo, vo = omlp.adam_step(po, g, mo, vo, s + 1)
+    # Adam normalises each step to ~lr per parameter, so compare in units of lr
+    assert np.max(np.abs(pg - po)) <= 0.02 * 1e-3 * steps
+    assert np.mean(np.abs(pg - po)) <= 1e-3 * 1e-3 * steps
+
+
+@pytest.mark.parametrize("k", [5, 30, 50])
+def test_predict_matches_oracle(k):
+    G, R = problems(k, 5000, 3 * k)
+    p = C.mlp_init(k, 77 + k)
+    rng = np.random.default_rng(k)
+    lay = C.mlp_layout(k)
+    p[lay["b3"][0]:lay["b3"][0] + k] = rng.standard_normal(k).astype(np.float32) * 0.5
+    masks = L.nmf_mlp_predict(cuda(G), cuda(R), cuda(p)).cpu().numpy().view(np.uint64)
+    phi = omlp.features(G, R.astype(np.float64))
+    mo, z = omlp.predict_masks(p.astype(np.float64), phi, k, pinned=oracle.pinned_set(G))
+    diff = masks ^ mo
+    agree = 1.0 - np.mean([bin(int(d)).count("1") for d in diff]) / k
+    print(f"k={k}: bitwise agreement {agree:.5f}")
+    # BF16 operands: decisions may differ only where the logit is small
+    margin = 0.05 * np.abs(z).max()
+    for b in np.nonzero(diff)[0]:
+        bits = [i for i in range(k) if (int(diff[b]) >> i) & 1]
+        assert np.all(np.abs(z[b, bits]) <= margin), (b, bits, z[b, bits])
+    assert agree >= 0.99
+
+
+def test_learned_warm_start_in_anls():
+    """Train the W- and H-side networks on samples collected by the driver,
+    then run with the learned warm start: the trajectory matches the cold
+    oracle (the warm start cannot change the unique solutions) and needs fewer
+    solves than cold."""
+    seed, m, n, k = C.seed_for(5), 6000, 2400, 30
+    from nmf_inputs import device as gen
+    Ad = gen.video(seed, m, n)
+    A = Ad.cpu().numpy()
+    W0, H0 = C.init_w(seed, m, k), C.init_ht(seed, n, k)
+    T1, T2 = 3, 3
+    ref = oracle.anls(k, W0, H0, T1 + T2, dense=A)
+    M = L.Matrix(dense=Ad)
+    W, Ht = cuda(W0), cuda(H0)
+    sw, sh = 4, 1
+    cap_w, cap_h = T1 * ((m + sw - 1) // sw), T1 * ((n + sh - 1) // sh)
+    phi_w = torch.zeros((cap_w, 2 * k), dtype=torch.float32, device="cuda")
+    phi_h = torch.zeros((cap_h, 2 * k), dtype=torch.float32, device="cuda")
+    mk_w = torch.zeros(cap_w, dtype=torch.int64, device="cuda")
+    mk_h = torch.zeros(cap_h, dtype=torch.int64, device="cuda")
+    o = L.make_opts()
+    o.collect, o.collect_stride_w, o.collect_stride_h = 1, sw, sh
+    o.coll_phi_w, o.coll_mask_w, o.coll_cap_w = phi_w.data_ptr(), mk_w.data_ptr(), cap_w
+    o.coll_phi_h, o.coll_mask_h, o.coll_cap_h = phi_h.data_ptr(), mk_h.data_ptr(), cap_h
+    st1 = L.new_stats(T1)
+    L.nmf_anls_iter(M, k, W, Ht, T1, o, st1)
+    tw = L.MlpTrainer(k, cuda(C.mlp_init(k, seed, side=0)), batch=512)
+    th = L.MlpTrainer(k, cuda(C.mlp_init(k, seed, side=1)), batch=512)
+    lw0 = tw.train(phi_w, mk_w, cap_w, 1).item()
+    lw = tw.train(phi_w, mk_w, cap_w, 300).item()
+    th.train(phi_h, mk_h, cap_h, 300)
+    print(f"W-side loss {lw0:.4f} -> {lw:.4f}")
+    assert lw < lw0
+    o2 = L.make_opts(warm=L.NMF_WARM_LEARNED, net_w=tw.params, net_h=th.params, reset_masks=True)
+    st2 = L.new_stats(T2)
+    L.nmf_anls_iter(M, k, W, Ht, T2, o2, st2)
+    s1, s2 = L.decode_stats(st1), L.decode_stats(st2)
+    rf = np.array([s["r_full"] for s in s1 + s2])
+    assert np.max(np.abs(rf - ref["r_full"])) <= 1e-5
+    solves_learned = sum(s["bpp_w"][1] for s in s2)
+    rounds_cold_oracle = ref["rounds_w"][T1:].sum()
+    print(f"W solves with learned start {solves_learned}, cold rounds (oracle) {rounds_cold_oracle}, "
+          f"fallbacks {sum(s['fallback'] for s in s2)}")
+    assert sum(s["capped"] for s in s2) == 0
