@@ -1,0 +1,374 @@
+#!/usr/bin/env python3
+"""ANLS-BPP NMF benchmark on one MI355X.
+
+Workload: the video-like dense matrix, 1,000,000 x 2,400 (FP32, 9.6 GB, built
+in HBM by the seeded generator), rank k = 30, 50 ANLS-BPP iterations from the
+seeded U[0,1) initial factors.  One step is one such 50-iteration run:
+
+  learned + BF16x3 form (the reported value): iterations 1-5 with cold BPP
+    and BF16x3 right-hand sides while collecting (features, final passive
+    set) samples, training of the W-side and H-side warm-start networks on
+    the GPU, iterations 6-50 with the networks' start sets;
+  plain FP32 form (timed beside it): 50 iterations, cold BPP, FP32 MFMA
+    right-hand sides.
+
+value = iterations / second of the learned + BF16x3 form (training included),
+with the inputs (A, its BF16 planes, the initial factors) resident in HBM.
+Both forms' final relative objective is checked against the FP64 oracle's
+trajectory (tests/golden/video_1e6x2400_k30_oracle.json) when available.
+
+Per-phase HIP events inside the timed region give the dominant kernel's
+average duration for the roofline; the FP64 CPU oracle is timed on a bounded
+row sample for the CPU baseline.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ANLS-BPP iters/sec at matched rel. objective (learned+BF16 vs plain FP32)"
+GOLDEN = os.path.join(ROOT, "tests", "golden", "video_1e6x2400_k30_oracle.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=1_000_000)
+    ap.add_argument("--n", type=int, default=2_400)
+    ap.add_argument("--k", type=int, default=30)
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--cold-iters", type=int, default=5)
+    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-batch", type=int, default=1024)
+    ap.add_argument("--collect-stride", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--pmc", action="store_true", help="copy calibration + dominant kernels only (for rocprofv3 --pmc)")
+    return ap.parse_args()
+
+
+class Bench:
+    def __init__(self, a):
+        import torch
+
+        from nmf_inputs import configs as C
+        from nmf_inputs import device as gen
+        from paper_1509_09313_amd import binding as L
+        self.torch, self.C, self.L, self.a = torch, C, L, a
+        self.seed = C.seed_for(5)
+        m, n, k = a.m, a.n, a.k
+        t0 = time.perf_counter()
+        self.A = gen.video(self.seed, m, n)
+        self.W0, self.Ht0 = gen.init_factors(self.seed, m, n, k)
+        self.M = L.Matrix(dense=self.A)
+        torch.cuda.synchronize()
+        self.t_gen = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        self.M.add_split()
+        torch.cuda.synchronize()
+        self.t_split = time.perf_counter() - t0
+        self.W = torch.empty_like(self.W0)
+        self.Ht = torch.empty_like(self.Ht0)
+        # learned form: collection buffers, networks, runners
+        self.T1 = a.cold_iters
+        self.T2 = a.iters - a.cold_iters
+        sw, sh = a.collect_stride, 1
+        self.cap_w = self.T1 * ((m + sw - 1) // sw)
+        self.cap_h = self.T1 * ((n + sh - 1) // sh)
+        f32, i64 = torch.float32, torch.int64
+        self.phi_w = torch.zeros((self.cap_w, 2 * k), dtype=f32, device="cuda")
+        self.phi_h = torch.zeros((self.cap_h, 2 * k), dtype=f32, device="cuda")
+        self.mk_w = torch.zeros(self.cap_w, dtype=i64, device="cuda")
+        self.mk_h = torch.zeros(self.cap_h, dtype=i64, device="cuda")
+        o1 = L.make_opts(prec=L.NMF_BF16X3, trace=True, reset_masks=True)
+        o1.collect, o1.collect_stride_w, o1.collect_stride_h = 1, sw, sh
+        o1.coll_phi_w, o1.coll_mask_w, o1.coll_cap_w = self.phi_w.data_ptr(), self.mk_w.data_ptr(), self.cap_w
+        o1.coll_phi_h, o1.coll_mask_h, o1.coll_cap_h = self.phi_h.data_ptr(), self.mk_h.data_ptr(), self.cap_h
+        self.pw0 = torch.from_numpy(C.mlp_init(k, self.seed, side=0)).cuda()
+        self.ph0 = torch.from_numpy(C.mlp_init(k, self.seed, side=1)).cuda()
+        self.tw = L.MlpTrainer(k, self.pw0.clone(), batch=a.train_batch)
+        self.th = L.MlpTrainer(k, self.ph0.clone(), batch=a.train_batch)
+        o2 = L.make_opts(prec=L.NMF_BF16X3, warm=L.NMF_WARM_LEARNED, net_w=self.tw.params, net_h=self.th.params,
+                         trace=True, reset_masks=True)
+        self.run1 = L.Anls(self.M, k, o1)
+        self.run2 = L.Anls(self.M, k, o2)
+        self.st1 = L.new_stats(self.T1)
+        self.st2 = L.new_stats(self.T2)
+        oP = L.make_opts(prec=L.NMF_F32, trace=True, reset_masks=True)
+        self.runP = L.Anls(self.M, k, oP)
+        self.stP = L.new_stats(a.iters)
+
+    # ---------------------------------------------------------------- forms --
+    def learned_step(self, timers=None):
+        t = self.torch
+        self.W.copy_(self.W0)
+        self.Ht.copy_(self.Ht0)
+        if timers:
+            timers[0].attach(self.run1.opts)
+            timers[1].attach(self.run2.opts)
+        self.run1.run(self.W, self.Ht, self.T1, self.st1)
+        for tr, p0, phi, mk, cap in ((self.tw, self.pw0, self.phi_w, self.mk_w, self.cap_w),
+                                     (self.th, self.ph0, self.phi_h, self.mk_h, self.cap_h)):
+            tr.params.copy_(p0)
+            tr.m.zero_()
+            tr.v.zero_()
+            tr.step = 0
+            tr.train(phi, mk, cap, self.a.train_steps)
+        self.run2.run(self.W, self.Ht, self.T2, self.st2)
+        if timers:
+            timers[0].detach(self.run1.opts)
+            timers[1].detach(self.run2.opts)
+        del t
+
+    def plain_step(self, timer=None):
+        self.W.copy_(self.W0)
+        self.Ht.copy_(self.Ht0)
+        if timer:
+            timer.attach(self.runP.opts)
+        self.runP.run(self.W, self.Ht, self.a.iters, self.stP)
+        if timer:
+            timer.detach(self.runP.opts)
+
+    def final_r(self):
+        return float(self.L.nmf_objective(self.M, self.W, self.Ht)[0].item())
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def bpp_flops(stats, k, key):
+    """Algorithmic FP64 flops of the passive-set solves (Cholesky count):
+    sum over solves of |F|^3/3 + 2|F|^2 + 2k|F| (solve, two triangular
+    sweeps, dual)."""
+    tot = 0.0
+    for s in stats:
+        c = s[key]
+        tot += c[4] / 3.0 + 2.0 * c[3] + 2.0 * k * c[2]
+    return tot
+
+
+def roofline(bench, timers_l, stats_l):
+    """Dominant kernel of the learned form over the timed region."""
+    a = bench.a
+    L = bench.L
+    per = {p: [] for p in L.PHASES}
+    for tm in timers_l:
+        ph = tm.phase_ms()
+        for p in L.PHASES:
+            per[p] += ph[p]
+    totals = {p: sum(v) for p, v in per.items()}
+    launches = {p: len(v) for p, v in per.items()}
+    dom = max(("rhs_w", "rhs_h", "bpp_w", "bpp_h", "gram_w", "gram_h", "infer_w", "infer_h"), key=lambda p: totals[p])
+    avg_ms = totals[dom] / max(1, launches[dom])
+    m, n, k = a.m, a.n, a.k
+    out = {"kernel_phase": dom, "avg_ms": avg_ms,
+           "phase_ms_per_iter": {p: totals[p] / max(1, launches[p]) for p in L.PHASES}}
+    if dom in ("rhs_w", "rhs_h"):
+        rows = m if dom == "rhs_w" else n
+        contracted = n if dom == "rhs_w" else m
+        alg_bytes = 4.0 * m * n + 4.0 * contracted * k + 4.0 * rows * k
+        ach = alg_bytes / (avg_ms * 1e-3) / 1e9
+        out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                   algorithmic_bytes_per_launch=alg_bytes)
+    elif dom in ("bpp_w", "bpp_h"):
+        key = "bpp_w" if dom == "bpp_w" else "bpp_h"
+        # counters of the last timed step (every step repeats the same run)
+        n_it = sum(len(s) for s in stats_l)
+        fl = sum(bpp_flops(s, k, key) for s in stats_l) / max(1, n_it)
+        ach = fl / (avg_ms * 1e-3) / 1e12
+        out.update(bound="alu", achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / FP64_PEAK_TFLOPS,
+                   algorithmic_flops_per_launch=fl)
+    else:
+        rows = m if dom in ("gram_w", "infer_w") else n
+        alg_bytes = 4.0 * rows * k
+        ach = alg_bytes / (avg_ms * 1e-3) / 1e9
+        out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                   algorithmic_bytes_per_launch=alg_bytes)
+    out["traffic"] = None
+    try:
+        with open(TRAFFIC) as fh:
+            tr = json.load(fh)
+        ent = tr.get(dom)
+        if ent and ent.get("source_sha256") == source_digest():
+            out["traffic"] = ent["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    return out
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1509_09313_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(bench, seconds):
+    """The FP64 oracle (as it stands) on the first S rows: one ANLS-BPP
+    iteration, time scaled by m / S to the full matrix."""
+    import numpy as np
+
+    import oracle
+    a = bench.a
+    torch = bench.torch
+    W0 = bench.W0.cpu().numpy()
+    H0 = bench.Ht0.cpu().numpy()
+
+    def one(S):
+        A = bench.A[:S].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.anls(a.k, W0[:S], H0, 1, dense=A)
+        return time.perf_counter() - t0
+
+    S = min(a.m, 20_000)
+    t = one(S)
+    S2 = int(min(a.m, max(S, S * seconds / max(t, 1e-3))))
+    if S2 > S:
+        S, t = S2, one(S2)
+    per_iter = t * a.m / S
+    del torch
+    return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"1 ANLS-BPP iteration of the FP64 oracle on rows 0..{S - 1} ({S} x {a.n}, k={a.k}), "
+                      f"{t:.2f} s, scaled by {a.m}/{S} to the full matrix",
+            "seconds_per_iter_full": per_iter}
+
+
+def pmc_mode(a):
+    """Launches a plain copy of known size, then the dominant kernels a few
+    times each, for rocprofv3 counter collection (FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    b = Bench(a)
+    L = b.L
+    src = torch.empty(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    bt, btt = b.M.tiled
+    for _ in range(3):
+        L.nmf_rhs_dense(L.NMF_SIDE_W, None, b.Ht0, prec=L.NMF_BF16X3, B_bf16=bt, m=a.m, n=a.n)
+        L.nmf_rhs_dense(L.NMF_SIDE_H, None, b.W0, prec=L.NMF_BF16X3, B_bf16=btt, m=a.m, n=a.n)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc": "done", "copy_bytes": 2 * src.numel() * 4}))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (this build runs on a single MI355X)",
+              file=sys.stderr)
+        sys.exit(2)
+    if a.pmc:
+        pmc_mode(a)
+        return
+    import numpy as np
+    b = Bench(a)
+    L = b.L
+    print(f"# inputs: generate {b.t_gen:.2f}s, one-time BF16 split {b.t_split:.3f}s", file=sys.stderr, flush=True)
+
+    # learned + BF16x3 form, with per-phase events over the timed steps
+    timers = [(L.PhaseTimer(b.T1), L.PhaseTimer(b.T2)) for _ in range(a.steps)]
+    it = iter(timers)
+    for _ in range(a.warmup):
+        b.learned_step()
+    b.torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        b.learned_step(next(it))
+    b.torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    r_learned = b.final_r()
+    st_l = L.decode_stats(b.st1) + L.decode_stats(b.st2)
+    print(f"# learned+bf16x3: {t_learned / a.steps * 1e3:.1f} ms/step, final r {r_learned:.8f}", file=sys.stderr,
+          flush=True)
+    roof = roofline(b, [t for pair in timers for t in pair], [L.decode_stats(b.st1), L.decode_stats(b.st2)])
+
+    plain = None
+    if not a.no_plain:
+        tp = L.PhaseTimer(a.iters)
+        t_plain = timed(b.plain_step, a.steps, a.warmup)
+        r_plain = b.final_r()
+        b.plain_step(tp)
+        b.torch.cuda.synchronize()
+        ph = tp.phase_ms()
+        st_p = L.decode_stats(b.stP)
+        plain = {"iters_per_s": a.iters * a.steps / t_plain, "ms_per_step": t_plain / a.steps * 1e3,
+                 "final_r": r_plain, "phase_ms_per_iter": {p: float(np.mean(v)) for p, v in ph.items()},
+                 "bpp_rounds_w_per_row": float(np.mean([s["bpp_w"][0] for s in st_p]) / a.m),
+                 "bpp_solves_w_per_row": float(np.mean([s["bpp_w"][1] for s in st_p]) / a.m)}
+        print(f"# plain fp32: {plain['ms_per_step']:.1f} ms/step, final r {r_plain:.8f}", file=sys.stderr, flush=True)
+
+    oracle_r = None
+    if os.path.exists(GOLDEN) and (a.m, a.n, a.k, a.iters) == (1_000_000, 2_400, 30, 50):
+        with open(GOLDEN) as fh:
+            oracle_r = json.load(fh)["r_full"][-1]
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(b, a.cpu_seconds)
+
+    value = a.iters * a.steps / t_learned
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": t_learned / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3 products (fp32 accumulate) + f64 Gram/BPP",
+        "data": "synthetic",
+        "config": {"workload": f"video-like dense {a.m}x{a.n} (rank-10 background + 2% foreground), k={a.k}, "
+                               f"{a.iters} ANLS-BPP iterations per step; learned warm start after {a.cold_iters} "
+                               f"cold iterations + BF16x3 right-hand sides",
+                   "m": a.m, "n": a.n, "k": a.k, "iters_per_step": a.iters, "train_steps": a.train_steps,
+                   "train_batch": a.train_batch, "collect_stride_w": a.collect_stride},
+        "final_r": r_learned,
+        "oracle_r": oracle_r,
+        "abs_dr_vs_oracle": None if oracle_r is None else abs(r_learned - oracle_r),
+        "plain_fp32": plain,
+        "speedup_vs_plain_fp32": None if plain is None else value / plain["iters_per_s"],
+        "matched_objective": None if plain is None else abs(r_learned - plain["final_r"]) <= 1e-5,
+        "bpp_solves_w_per_row_learned": float(np.mean([s["bpp_w"][1] for s in st_l[b.T1:]]) / a.m),
+        "bpp_fallbacks_learned": int(sum(s["fallback"] for s in st_l)),
+        "one_time_split_s": b.t_split,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    for pair in timers:
+        for t in pair:
+            t.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

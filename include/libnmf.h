@@ -67,8 +67,9 @@ extern "C" {
 
 /* BPP counters (device array of NMF_BPP_COUNTERS uint64, accumulated, optional):
  * [0] KKT checks (rounds), [1] passive-set solves (rounds with F nonempty),
- * [2] sum |F|, [3] sum |F|^2, [4] sum |F|^3, each over the solves. */
-#define NMF_BPP_COUNTERS 5
+ * [2] sum |F|, [3] sum |F|^2, [4] sum |F|^3, each over the solves,
+ * [5] elimination (pivot) steps executed. */
+#define NMF_BPP_COUNTERS 6
 
 const char* nmf_last_error(void);
 const char* nmf_version(void);
@@ -78,7 +79,7 @@ const char* nmf_version(void);
  * leading dimension ldx >= k).  With X = Ht this is H H^T, with X = W it is
  * W^T W (Algorithm 1, both updates; the local Gram of Algorithm 3).  FP32
  * products are exact in FP64 and are summed in FP64 in a fixed order, so the
- * result is deterministic.  rows == 0 gives G = 0. */
+ * result is deterministic.  rows == 0 gives G = 0 (X and ldx unused). */
 int nmf_gram_workspace_bytes(int64_t rows, int k, size_t* bytes);
 int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* ws, size_t ws_bytes,
              void* stream);
@@ -89,23 +90,26 @@ int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* 
  * A: FP32 m x n, leading dimension lda >= n (device).
  * prec NMF_F32: FP32 MFMA with FP32 accumulation (side H: split over rows of
  *   A with a deterministic FP64 sum of the FP32 partials).
- * prec NMF_BF16X3: the operand whose columns are contracted is given as two
- *   BF16 planes from nmf_split_bf16: for side W the planes of A (m x n), for
- *   side H the planes of A^T (n x m), leading dimension ldb.  Y is split in
- *   the workspace each call; R = hi*hi + hi*lo + lo*hi (lo*lo dropped),
- *   FP32 accumulation.  A itself is not read in this mode and may be NULL.
+ * prec NMF_BF16X3: the operand whose rows are the output rows is given in the
+ *   padded BF16 form of nmf_split_bf16: for side W that of A (transpose 0),
+ *   for side H that of A^T (transpose 1).  Y is split in the workspace each
+ *   call; R = hi*hi + hi*lo + lo*hi (lo*lo dropped), FP32 accumulation.  A
+ *   itself is not read in this mode and may be NULL.
  * R: FP32, leading dimension ldr >= k (device). */
 int nmf_rhs_dense_workspace_bytes(int side, int64_t m, int64_t n, int k, int prec, size_t* bytes);
-int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda,
-                  const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y, int64_t ldy,
-                  float* R, int64_t ldr, int prec, void* ws, size_t ws_bytes, void* stream);
+int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* B_bf16,
+                  const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* ws, size_t ws_bytes,
+                  void* stream);
 
-/* One-time split of an FP32 matrix X (rows x cols, ldx) into BF16 planes:
- * hi = bf16_rne(x), lo = bf16_rne(x - hi) (x - hi is exact in FP32).
- * transpose = 0 writes planes of X (rows x cols, ld ldo); transpose = 1 writes
- * the planes of X^T (cols x rows, ld ldo).  hi, lo: device uint16 buffers. */
-int nmf_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* hi, uint16_t* lo,
-                   int64_t ldo, int transpose, void* stream);
+/* One-time split of an FP32 matrix X (rows x cols, ldx) into the padded BF16
+ * form: the operand B = X (transpose 0) or B = X^T (transpose 1), rows_B x
+ * cols_B, is stored as two row-major planes of Rp x Cp BF16 values (Rp =
+ * rows_B rounded up to 128, Cp = cols_B rounded up to 64, zero padding): the
+ * hi plane, then the lo plane, hi = bf16_rne(x), lo = bf16_rne(x - hi)
+ * (x - hi is exact in FP32).  The 4 bytes per entry of A are kept.
+ * nmf_split_bf16_bytes gives the size of `out` (device). */
+size_t nmf_split_bf16_bytes(int64_t rows, int64_t cols, int transpose);
+int nmf_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, int transpose, void* out, void* stream);
 
 /* ---- sparse right-hand side -----------------------------------------------
  * R (rows x k) = A_csr (rows x cols) * Y (cols x k, ldy >= k).  Pass CSR(A)
@@ -177,12 +181,8 @@ typedef struct nmf_matrix {
   /* dense */
   const float* A;           /* m x n FP32, leading dimension lda (device) */
   int64_t lda;
-  const uint16_t* A_hi;     /* BF16X3 only: planes of A   (m x n, ld ld_hl) */
-  const uint16_t* A_lo;
-  int64_t ld_hl;
-  const uint16_t* At_hi;    /* BF16X3 only: planes of A^T (n x m, ld ld_hl_t) */
-  const uint16_t* At_lo;
-  int64_t ld_hl_t;
+  const void* A_bf16;       /* BF16X3 only: padded BF16 form of A   (nmf_split_bf16, transpose 0) */
+  const void* At_bf16;      /* BF16X3 only: padded BF16 form of A^T (nmf_split_bf16, transpose 1) */
   /* sparse */
   int64_t nnz;              /* number of stored entries (both CSR copies) */
   const int64_t* rowptr;    /* CSR(A):   m + 1 */
@@ -240,7 +240,31 @@ typedef struct nmf_opts {
   uint64_t* coll_mask_h;
   int64_t coll_cap_h;
   int64_t coll_off_h;
+  /* optional phase timing: hipEvent_t handles (from nmf_events_create);
+   * iteration t records events[2 * (t * NMF_PHASES + ph)] before phase ph and
+   * the next entry after it; entries beyond phase_events_cap are skipped.
+   * For the product phases the pair brackets the main product kernel only. */
+  void** phase_events;
+  int phase_events_cap;
 } nmf_opts;
+
+/* phases of one iteration, for nmf_opts.phase_events */
+#define NMF_PH_RHS_W 0    /* A H^T (main kernel) */
+#define NMF_PH_INFER_W 1  /* warm-start network, W side */
+#define NMF_PH_BPP_W 2    /* NNLS for the rows of W */
+#define NMF_PH_GRAM_W 3   /* W^T W */
+#define NMF_PH_RHS_H 4    /* W^T A (main kernel) */
+#define NMF_PH_INFER_H 5
+#define NMF_PH_BPP_H 6
+#define NMF_PH_GRAM_H 7   /* H H^T */
+#define NMF_PH_OTHER 8    /* objective, statistics, sample collection */
+#define NMF_PHASES 9
+
+/* Host helpers for timing: create / destroy n hipEvent_t handles, and the
+ * elapsed milliseconds between two recorded events (after they complete). */
+int nmf_events_create(int n, void** events);
+int nmf_events_destroy(int n, void** events);
+int nmf_events_elapsed_ms(void* start, void* stop, float* ms);
 
 /* Per-iteration statistics, written to a device array of `iters` entries. */
 typedef struct nmf_iter_stats {

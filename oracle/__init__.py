@@ -66,6 +66,7 @@ def lib():
         L.orc_anls.argtypes = [ctypes.POINTER(_Matrix), ci, vp, vp, ci, ci, ci, ci, cd, vp, vp, vp, vp,
                                vp, vp, vp]
         L.orc_anls.restype = ci
+        L.orc_max_threads.restype = ci
         _lib = L
     return _lib
 
@@ -221,6 +222,10 @@ def anls(k, W0, Ht0, T, *, dense=None, csr=None, csr_t=None, shape=None, max_rou
         raise MemoryError("oracle ANLS could not allocate its buffers")
     return dict(W=W, Ht=Ht, r_half=r_half, r_full=r_full, rounds_w=rw, rounds_h=rh,
                 capped=int(cap.value), masks_w=mw, masks_h=mh, fro2=fro2)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def kkt_residuals(G, f, x):

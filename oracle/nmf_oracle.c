@@ -405,3 +405,7 @@ int orc_anls(const orc_matrix* A, int k, double* W, double* Ht, int T, int max_r
   free(RW); free(RH); free(MW); free(MH); free(rnd); free(sts);
   return 0;
 }
+
+/* Threads the OpenMP loops above use (reported with the CPU baseline). */
+#include <omp.h>
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -20,7 +20,9 @@ NMF_DENSE, NMF_CSR = 0, 1
 NMF_OBJ_DIRECT, NMF_OBJ_TRACE = 0, 1
 NMF_WARM_COLD, NMF_WARM_PREV, NMF_WARM_LEARNED = 0, 1, 2
 NMF_BPP_WARM_FALLBACK, NMF_BPP_CAPPED, NMF_BPP_PINNED, NMF_BPP_SINGULAR = 1, 2, 4, 8
-NMF_BPP_COUNTERS = 5
+NMF_BPP_COUNTERS = 6
+PHASES = ("rhs_w", "infer_w", "bpp_w", "gram_w", "rhs_h", "infer_h", "bpp_h", "gram_h", "other")
+NMF_PHASES = len(PHASES)
 
 
 class NmfError(RuntimeError):
@@ -37,8 +39,7 @@ ci = ctypes.c_int
 class nmf_matrix(ctypes.Structure):
     _fields_ = [("kind", ci), ("m", i64), ("n", i64),
                 ("A", vp), ("lda", i64),
-                ("A_hi", vp), ("A_lo", vp), ("ld_hl", i64),
-                ("At_hi", vp), ("At_lo", vp), ("ld_hl_t", i64),
+                ("A_bf16", vp), ("At_bf16", vp),
                 ("nnz", i64),
                 ("rowptr", vp), ("colidx", vp), ("vals", vp),
                 ("rowptr_t", vp), ("colidx_t", vp), ("vals_t", vp),
@@ -51,7 +52,8 @@ class nmf_opts(ctypes.Structure):
                 ("net_w", vp), ("net_h", vp),
                 ("collect", ci), ("collect_stride_w", ci), ("collect_stride_h", ci),
                 ("coll_phi_w", vp), ("coll_mask_w", vp), ("coll_cap_w", i64), ("coll_off_w", i64),
-                ("coll_phi_h", vp), ("coll_mask_h", vp), ("coll_cap_h", i64), ("coll_off_h", i64)]
+                ("coll_phi_h", vp), ("coll_mask_h", vp), ("coll_cap_h", i64), ("coll_off_h", i64),
+                ("phase_events", ctypes.POINTER(vp)), ("phase_events_cap", ci)]
 
 
 class nmf_iter_stats(ctypes.Structure):
@@ -81,9 +83,9 @@ def lib():
             "nmf_gram_workspace_bytes": ([i64, ci, sz], ci),
             "nmf_gram": ([i64, ci, vp, i64, vp, vp, ctypes.c_size_t, vp], ci),
             "nmf_rhs_dense_workspace_bytes": ([ci, i64, i64, ci, ci, sz], ci),
-            "nmf_rhs_dense": ([ci, i64, i64, ci, vp, i64, vp, vp, i64, vp, i64, vp, i64, ci, vp, ctypes.c_size_t,
-                               vp], ci),
-            "nmf_split_bf16": ([i64, i64, vp, i64, vp, vp, i64, ci, vp], ci),
+            "nmf_rhs_dense": ([ci, i64, i64, ci, vp, i64, vp, vp, i64, vp, i64, ci, vp, ctypes.c_size_t, vp], ci),
+            "nmf_split_bf16_bytes": ([i64, i64, ci], ctypes.c_size_t),
+            "nmf_split_bf16": ([i64, i64, vp, i64, ci, vp, vp], ci),
             "nmf_rhs_csr": ([i64, i64, ci, vp, vp, vp, vp, i64, vp, i64, vp], ci),
             "nnls_bpp_batched": ([ci, i64, vp, vp, i64, vp, i64, vp, vp, vp, vp, ci, ci, vp, vp], ci),
             "nmf_fro2_workspace_bytes": ([M, sz], ci),
@@ -93,6 +95,9 @@ def lib():
             "nmf_anls_workspace_bytes": ([M, ci, O, sz], ci),
             "nmf_anls_iter": ([M, ci, vp, vp, ci, O, vp, vp, ctypes.c_size_t, vp], ci),
             "nmf_mlp_param_count": ([ci], ci),
+            "nmf_events_create": ([ci, ctypes.POINTER(vp)], ci),
+            "nmf_events_destroy": ([ci, ctypes.POINTER(vp)], ci),
+            "nmf_events_elapsed_ms": ([vp, vp, ctypes.POINTER(ctypes.c_float)], ci),
             "nmf_features": ([ci, i64, vp, vp, i64, vp, vp], ci),
             "nmf_mlp_predict": ([ci, i64, vp, vp, i64, vp, vp, vp], ci),
             "nmf_mlp_train_workspace_bytes": ([ci, ci, sz], ci),
@@ -157,20 +162,27 @@ def nmf_gram(X, G=None):
 
 
 def nmf_split_bf16(X, transpose=False):
-    """(hi, lo) int16 planes of X (or of X^T if transpose)."""
+    """Padded BF16 (hi, lo) form of X (or of X^T) as a uint8 device buffer."""
     _dev(X, torch.float32, "X")
     rows, cols = X.shape
-    shape = (cols, rows) if transpose else (rows, cols)
-    hi = torch.empty(shape, dtype=torch.int16, device="cuda")
-    lo = torch.empty(shape, dtype=torch.int16, device="cuda")
-    _check(lib().nmf_split_bf16(rows, cols, _ptr(X), _ld(X), _ptr(hi), _ptr(lo), shape[1], int(transpose),
-                                _stream()))
-    return hi, lo
+    nb = lib().nmf_split_bf16_bytes(rows, cols, int(transpose))
+    out = torch.empty(max(int(nb), 16), dtype=torch.uint8, device="cuda")
+    _check(lib().nmf_split_bf16(rows, cols, _ptr(X), _ld(X), int(transpose), _ptr(out), _stream()))
+    return out
 
 
-def nmf_rhs_dense(side, A, Y, R=None, prec=NMF_F32, B_hi=None, B_lo=None, m=None, n=None):
+def unpack_bf16(buf, rows, cols):
+    """Host helper for tests: (hi, lo) uint16 arrays (rows x cols) of the
+    padded BF16 form of an operand with `rows` rows and `cols` columns."""
+    import numpy as np
+    Rp, Cp = -(-rows // 128) * 128, -(-cols // 64) * 64
+    t = buf.cpu().numpy().view(np.uint16).reshape(2, Rp, Cp)
+    return t[0, :rows, :cols], t[1, :rows, :cols]
+
+
+def nmf_rhs_dense(side, A, Y, R=None, prec=NMF_F32, B_bf16=None, m=None, n=None):
     """side W: R = A @ Y (Y = Ht); side H: R = A^T @ Y (Y = W).  For BF16X3
-    pass the planes of A (side W) or of A^T (side H) as B_hi / B_lo."""
+    pass the padded BF16 form of A (side W) or of A^T (side H) as B_bf16."""
     _dev(Y, torch.float32, "Y")
     k = Y.shape[1]
     if A is not None:
@@ -182,9 +194,8 @@ def nmf_rhs_dense(side, A, Y, R=None, prec=NMF_F32, B_hi=None, B_lo=None, m=None
     nb = ctypes.c_size_t(0)
     _check(lib().nmf_rhs_dense_workspace_bytes(side, m, n, k, prec, ctypes.byref(nb)))
     ws = _ws(nb.value)
-    ldb = _ld(B_hi) if B_hi is not None else (n if side == NMF_SIDE_W else m)
-    _check(lib().nmf_rhs_dense(side, m, n, k, _ptr(A), _ld(A) if A is not None else n, _ptr(B_hi), _ptr(B_lo), ldb,
-                               _ptr(Y), _ld(Y), _ptr(R), _ld(R), prec, _ptr(ws), nb.value, _stream()))
+    _check(lib().nmf_rhs_dense(side, m, n, k, _ptr(A), _ld(A) if A is not None else n, _ptr(B_bf16), _ptr(Y), _ld(Y),
+                               _ptr(R), _ld(R), prec, _ptr(ws), nb.value, _stream()))
     return R
 
 
@@ -252,12 +263,11 @@ class Matrix:
             self.add_split()
 
     def add_split(self):
-        hi, lo = nmf_split_bf16(self.A)
-        hit, lot = nmf_split_bf16(self.A, transpose=True)
-        self.keep += [hi, lo, hit, lot]
-        self.planes = (hi, lo, hit, lot)
-        self.s.A_hi, self.s.A_lo, self.s.ld_hl = hi.data_ptr(), lo.data_ptr(), _ld(hi)
-        self.s.At_hi, self.s.At_lo, self.s.ld_hl_t = hit.data_ptr(), lot.data_ptr(), _ld(hit)
+        bt = nmf_split_bf16(self.A)
+        btt = nmf_split_bf16(self.A, transpose=True)
+        self.keep += [bt, btt]
+        self.tiled = (bt, btt)
+        self.s.A_bf16, self.s.At_bf16 = bt.data_ptr(), btt.data_ptr()
 
     def ref(self):
         return ctypes.byref(self.s)
@@ -383,3 +393,41 @@ class MlpTrainer:
                                    self.step, _ptr(self.loss), _ptr(self.ws), self.ws_bytes, _stream()))
         self.step += steps
         return self.loss
+
+
+class PhaseTimer:
+    """hipEvent pairs around every phase of `iters` ANLS iterations (see
+    nmf_opts.phase_events); read back after the stream has completed."""
+
+    def __init__(self, iters):
+        self.iters = iters
+        self.n = 2 * NMF_PHASES * iters
+        self.events = (vp * self.n)()
+        _check(lib().nmf_events_create(self.n, self.events))
+
+    def attach(self, opts):
+        opts.phase_events = self.events
+        opts.phase_events_cap = self.n
+        return opts
+
+    def detach(self, opts):
+        opts.phase_events = None
+        opts.phase_events_cap = 0
+        return opts
+
+    def phase_ms(self):
+        """{phase: [ms per iteration]} (the events must have completed)."""
+        out = {p: [] for p in PHASES}
+        ms = ctypes.c_float(0)
+        for t in range(self.iters):
+            for ph, name in enumerate(PHASES):
+                a = self.events[2 * (t * NMF_PHASES + ph)]
+                b = self.events[2 * (t * NMF_PHASES + ph) + 1]
+                _check(lib().nmf_events_elapsed_ms(a, b, ctypes.byref(ms)))
+                out[name].append(ms.value)
+        return out
+
+    def close(self):
+        if self.events is not None:
+            lib().nmf_events_destroy(self.n, self.events)
+            self.events = None

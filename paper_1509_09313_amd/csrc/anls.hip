@@ -10,6 +10,7 @@ namespace nmf {
 int trace_finish_launch(const double* fro2, const double* cross, const double* gdot, double* out, hipStream_t s);
 // warm-start network (mlp.hip)
 int mlp_infer_plan(int k, int64_t batch, Carver& c, void** scratch);
+int mlp_pack_launch(int k, const float* params, void* scratch, hipStream_t s);
 int mlp_infer_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, const float* params,
                      uint64_t* mask_out, void* scratch, hipStream_t s);
 int features_launch(int k, int64_t batch, int64_t stride, const double* G, const float* R, int64_t ldr, float* phi,
@@ -79,7 +80,8 @@ struct Plan {
   double* obj;
   double* dpart;
   int dblocks;
-  void* infer;
+  void* infer_w;
+  void* infer_h;
 };
 
 int plan_anls(const nmf_matrix* A, int k, const nmf_opts* o, nmf::Carver& c, Plan* P) {
@@ -102,8 +104,11 @@ int plan_anls(const nmf_matrix* A, int k, const nmf_opts* o, nmf::Carver& c, Pla
   P->gdot = c.take<double>(1);
   P->obj = c.take<double>(4);
   nmf::dot_plan(mx * k, c, &P->dpart, &P->dblocks);
-  P->infer = nullptr;
-  if (o->warm == NMF_WARM_LEARNED) NMF_TRY(nmf::mlp_infer_plan(k, mx, c, &P->infer));
+  P->infer_w = P->infer_h = nullptr;
+  if (o->warm == NMF_WARM_LEARNED) {
+    NMF_TRY(nmf::mlp_infer_plan(k, mx, c, &P->infer_w));
+    NMF_TRY(nmf::mlp_infer_plan(k, mx, c, &P->infer_h));
+  }
   return NMF_OK;
 }
 
@@ -112,8 +117,8 @@ int check_opts(const nmf_matrix* A, const nmf_opts* o) {
   if (o->prec != NMF_F32 && o->prec != NMF_BF16X3) return nmf::fail(NMF_EINVAL, "nmf_anls: bad prec");
   if (o->prec == NMF_BF16X3 && A->kind != NMF_DENSE)
     return nmf::fail(NMF_EINVAL, "nmf_anls: BF16X3 needs a dense matrix");
-  if (o->prec == NMF_BF16X3 && (!A->A_hi || !A->A_lo || !A->At_hi || !A->At_lo))
-    return nmf::fail(NMF_EINVAL, "nmf_anls: BF16X3 needs the planes of A and A^T");
+  if (o->prec == NMF_BF16X3 && (!A->A_bf16 || !A->At_bf16))
+    return nmf::fail(NMF_EINVAL, "nmf_anls: BF16X3 needs the tiled BF16 forms of A and A^T");
   if (o->warm < NMF_WARM_COLD || o->warm > NMF_WARM_LEARNED) return nmf::fail(NMF_EINVAL, "nmf_anls: bad warm mode");
   if (o->warm == NMF_WARM_LEARNED && (!o->net_w || !o->net_h))
     return nmf::fail(NMF_EINVAL, "nmf_anls: learned warm start needs both networks");
@@ -146,10 +151,8 @@ int rhs(const nmf_matrix* A, int side, int k, int prec, const float* Y, float* R
       return nmf::rhs_csr_launch(A->m, A->n, k, A->rowptr, A->colidx, A->vals, Y, k, R, k, s);
     return nmf::rhs_csr_launch(A->n, A->m, k, A->rowptr_t, A->colidx_t, A->vals_t, Y, k, R, k, s);
   }
-  const uint16_t* bh = side == NMF_SIDE_W ? A->A_hi : A->At_hi;
-  const uint16_t* bl = side == NMF_SIDE_W ? A->A_lo : A->At_lo;
-  const int64_t ldb = side == NMF_SIDE_W ? A->ld_hl : A->ld_hl_t;
-  return nmf::rhs_dense_launch(side, A->m, A->n, k, A->A, A->lda, bh, bl, ldb, Y, k, R, k, prec, scratch, s);
+  const void* bt = side == NMF_SIDE_W ? A->A_bf16 : A->At_bf16;
+  return nmf::rhs_dense_launch(side, A->m, A->n, k, A->A, A->lda, bt, Y, k, R, k, prec, scratch, s);
 }
 
 int count_status(int64_t n, const uint8_t* status, nmf_iter_stats* st, hipStream_t s) {
@@ -216,7 +219,22 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
   int64_t hc[2] = {o->collect ? o->coll_off_w : 0, o->collect ? o->coll_off_h : 0};
 
   NMF_TRY(nmf::gram_launch(n, k, Ht, k, P.GH, P.gpart, P.gblocks, s));
+  if (o->warm == NMF_WARM_LEARNED) {
+    NMF_TRY(nmf::mlp_pack_launch(k, o->net_w, P.infer_w, s));
+    NMF_TRY(nmf::mlp_pack_launch(k, o->net_h, P.infer_h, s));
+  }
   const bool warm = o->warm != NMF_WARM_COLD;
+  auto ev = [&](int t, int ph, int which) -> hipEvent_t {
+    const int64_t idx = 2 * ((int64_t)t * NMF_PHASES + ph) + which;
+    return (o->phase_events && idx < o->phase_events_cap) ? static_cast<hipEvent_t>(o->phase_events[idx]) : nullptr;
+  };
+  auto rec = [&](hipEvent_t e) {
+    if (e) hipEventRecord(e, s);
+  };
+  struct MarkScope {  // brackets the main product kernel with the given events
+    MarkScope(hipEvent_t a, hipEvent_t b) { nmf::kernel_mark() = {a, b}; }
+    ~MarkScope() { nmf::kernel_mark() = {}; }
+  };
   for (int t = 0; t < iters; ++t) {
     nmf_iter_stats* st = stats ? stats + t : nullptr;
     if (st) {
@@ -225,16 +243,25 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
       NMF_TRY(nmf::launch_status("zero stats"));
     }
     // ---- W update: W = argmin ||A - W H||, from H H^T and A H^T
-    NMF_TRY(rhs(A, NMF_SIDE_W, k, o->prec, Ht, P.RW, P.rhs_w, s));
+    {
+      MarkScope mark(ev(t, NMF_PH_RHS_W, 0), ev(t, NMF_PH_RHS_W, 1));
+      NMF_TRY(rhs(A, NMF_SIDE_W, k, o->prec, Ht, P.RW, P.rhs_w, s));
+    }
+    rec(ev(t, NMF_PH_INFER_W, 0));
     if (o->warm == NMF_WARM_LEARNED)
-      NMF_TRY(nmf::mlp_infer_launch(k, m, P.GH, P.RW, k, o->net_w, P.MW, P.infer, s));
+      NMF_TRY(nmf::mlp_infer_launch(k, m, P.GH, P.RW, k, o->net_w, P.MW, P.infer_w, s));
+    rec(ev(t, NMF_PH_INFER_W, 1));
+    rec(ev(t, NMF_PH_BPP_W, 0));
     NMF_TRY(nmf::bpp_launch(k, m, P.GH, P.RW, k, W, k, warm ? P.MW : nullptr, P.MW, nullptr, P.status, o->max_rounds,
                             o->warm_cap, st ? st->bpp_w : nullptr, s));
+    rec(ev(t, NMF_PH_BPP_W, 1));
     if (st) NMF_TRY(count_status(m, P.status, st, s));
     if (o->collect)
       NMF_TRY(collect(k, m, o->collect_stride_w, P.GH, P.RW, P.MW, o->coll_phi_w, o->coll_mask_w, o->coll_cap_w,
                       &hc[0], s));
+    rec(ev(t, NMF_PH_GRAM_W, 0));
     NMF_TRY(nmf::gram_launch(m, k, W, k, P.GW, P.gpart, P.gblocks, s));
+    rec(ev(t, NMF_PH_GRAM_W, 1));
     if (st && o->trace_objective) {
       NMF_TRY(nmf::dot_f32_launch(m * k, P.RW, W, P.cross, P.dpart, P.dblocks, s));
       NMF_TRY(nmf::dot_f64_launch((int64_t)k * k, P.GW, P.GH, P.gdot, P.dpart, P.dblocks, s));
@@ -242,22 +269,33 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
       hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, s, P.obj, &st->r_half);
     }
     // ---- H update: H = argmin ||A - W H||, from W^T W and W^T A
-    NMF_TRY(rhs(A, NMF_SIDE_H, k, o->prec, W, P.RH, P.rhs_h, s));
+    {
+      MarkScope mark(ev(t, NMF_PH_RHS_H, 0), ev(t, NMF_PH_RHS_H, 1));
+      NMF_TRY(rhs(A, NMF_SIDE_H, k, o->prec, W, P.RH, P.rhs_h, s));
+    }
+    rec(ev(t, NMF_PH_INFER_H, 0));
     if (o->warm == NMF_WARM_LEARNED)
-      NMF_TRY(nmf::mlp_infer_launch(k, n, P.GW, P.RH, k, o->net_h, P.MH, P.infer, s));
+      NMF_TRY(nmf::mlp_infer_launch(k, n, P.GW, P.RH, k, o->net_h, P.MH, P.infer_h, s));
+    rec(ev(t, NMF_PH_INFER_H, 1));
+    rec(ev(t, NMF_PH_BPP_H, 0));
     NMF_TRY(nmf::bpp_launch(k, n, P.GW, P.RH, k, Ht, k, warm ? P.MH : nullptr, P.MH, nullptr, P.status, o->max_rounds,
                             o->warm_cap, st ? st->bpp_h : nullptr, s));
+    rec(ev(t, NMF_PH_BPP_H, 1));
     if (st) NMF_TRY(count_status(n, P.status, st, s));
     if (o->collect)
       NMF_TRY(collect(k, n, o->collect_stride_h, P.GW, P.RH, P.MH, o->coll_phi_h, o->coll_mask_h, o->coll_cap_h,
                       &hc[1], s));
+    rec(ev(t, NMF_PH_GRAM_H, 0));
     NMF_TRY(nmf::gram_launch(n, k, Ht, k, P.GH, P.gpart, P.gblocks, s));
+    rec(ev(t, NMF_PH_GRAM_H, 1));
+    rec(ev(t, NMF_PH_OTHER, 0));
     if (st && o->trace_objective) {
       NMF_TRY(nmf::dot_f32_launch(n * k, P.RH, Ht, P.cross, P.dpart, P.dblocks, s));
       NMF_TRY(nmf::dot_f64_launch((int64_t)k * k, P.GW, P.GH, P.gdot, P.dpart, P.dblocks, s));
       NMF_TRY(nmf::trace_finish_launch(A->fro2, P.cross, P.gdot, P.obj, s));
       hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, s, P.obj, &st->r_full);
     }
+    rec(ev(t, NMF_PH_OTHER, 1));
   }
   return nmf::launch_status("nmf_anls_iter");
 }

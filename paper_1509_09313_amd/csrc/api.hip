@@ -24,7 +24,36 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+KernelMark& kernel_mark() {
+  static thread_local KernelMark m;
+  return m;
+}
+
 }  // namespace nmf
+
+extern "C" int nmf_events_create(int n, void** events) {
+  if (n < 0 || (n > 0 && !events)) return nmf::fail(NMF_EINVAL, "nmf_events_create: bad arguments");
+  for (int i = 0; i < n; ++i) {
+    hipEvent_t e;
+    const hipError_t rc = hipEventCreate(&e);
+    if (rc != hipSuccess) return nmf::fail(NMF_EHIP, "nmf_events_create: %s", hipGetErrorString(rc));
+    events[i] = e;
+  }
+  return NMF_OK;
+}
+
+extern "C" int nmf_events_destroy(int n, void** events) {
+  for (int i = 0; i < n; ++i)
+    if (events[i]) hipEventDestroy(static_cast<hipEvent_t>(events[i]));
+  return NMF_OK;
+}
+
+extern "C" int nmf_events_elapsed_ms(void* start, void* stop, float* ms) {
+  if (!start || !stop || !ms) return nmf::fail(NMF_EINVAL, "nmf_events_elapsed_ms: null");
+  const hipError_t rc = hipEventElapsedTime(ms, static_cast<hipEvent_t>(start), static_cast<hipEvent_t>(stop));
+  if (rc != hipSuccess) return nmf::fail(NMF_EHIP, "nmf_events_elapsed_ms: %s", hipGetErrorString(rc));
+  return NMF_OK;
+}
 
 extern "C" const char* nmf_last_error(void) { return g_err; }
 

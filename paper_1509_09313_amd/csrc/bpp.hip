@@ -24,6 +24,17 @@
 // The infeasible set V = {p in F: x_p < 0} U {p not in F: y_p < 0} is a
 // ballot; the exchange rule is evaluated identically by every lane.
 //
+// Two forms of the same passive-set solve.  Each block also sweeps G once
+// (symmetric sweep operator over the unpinned indices U, FP64, index order)
+// to get G_U^{-1} in LDS, and each problem forms z = G_U^{-1} f.  When the
+// active part A = U \ F is smaller than F, the round eliminates over A on
+// (G^{-1}, z) instead of over F on (G, f): with v = ((G^{-1})_AA)^{-1} z_A,
+//     x_F = z_F - (G^{-1})_FA v       y_A = -v
+// (block inverse identities), so the common rounds with F = U or nearly so
+// cost |A| pivot steps instead of |F|.  This form is used only if every
+// sweep pivot of G exceeds 1e-6 G_jj (G well conditioned); otherwise, and
+// whenever a pivot of it fails, the round eliminates over F on G.
+//
 // Degenerate indices: an index with G_ii <= 1e-14 max_l G_ll is pinned at 0
 // from the start; a passive-subset pivot <= 1e-12 G_jj pins its index
 // (removed from F, never made passive again).  Pinned indices are excluded
@@ -45,6 +56,8 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
                                              unsigned long long* __restrict__ counters) {
   constexpr int P = 64 / K;
   __shared__ double Gs[K * K];
+  __shared__ double Gi[K * K];
+  __shared__ int inv_ok_s;
   __shared__ double colv[kWaves][64];
   __shared__ double rfv[kWaves][64];
   __shared__ unsigned long long cnt[kWaves][NMF_BPP_COUNTERS];
@@ -68,30 +81,107 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
   for (int q = 0; q < k; ++q)
     if (Gs[q * K + q] <= 1e-14 * dmax) pinned0 |= bit64(q);
 
-  unsigned long long c_rounds = 0, c_solves = 0, c_f1 = 0, c_f2 = 0, c_f3 = 0;
+  // G_U^{-1} by the symmetric sweep operator (one wavefront): sweeping index j
+  // maps a_jj -> -1/d, a_ij -> a_ij/d, a_il -> a_il - a_ij a_jl/d (d = a_jj);
+  // after sweeping all of U the U block holds -G_U^{-1}.  Lane i keeps row i,
+  // rotated left by one entry per step so that column j sits in r[0] at step
+  // j (the step loop then needs no register indexing by j).
+  if (wave == 0) {
+    const int pl = lane % K;
+    double r[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) r[q] = Gs[q * K + pl];
+    bool ok = true;
+    for (int j = 0; j < K; ++j) {
+      const bool sweep = j < k && !((pinned0 >> j) & 1ull);
+      if (sweep) {
+        colv[0][lane] = r[0];
+        wave_lds_sync();
+        const double d = colv[0][j];
+        if (!(d > 1e-6 * Gs[j * K + j])) ok = false;
+        const double inv = 1.0 / d;
+        const bool pivot_lane = pl == j;
+        const double m = r[0] * inv;
+#pragma unroll
+        for (int q = 1; q < K; ++q) {
+          const int col = (j + q) % K;
+          r[q] = pivot_lane ? r[q] * inv : r[q] - m * colv[0][col];
+        }
+        r[0] = pivot_lane ? -inv : m;
+        wave_lds_sync();
+      }
+      const double first = r[0];
+#pragma unroll
+      for (int q = 0; q < K - 1; ++q) r[q] = r[q + 1];
+      r[K - 1] = first;
+    }
+    if (lane < K) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const bool inU = q < k && pl < k && !((pinned0 >> q) & 1ull) && !((pinned0 >> pl) & 1ull);
+        Gi[q * K + pl] = inU ? -r[q] : 0.0;
+      }
+    }
+    if (lane == 0) inv_ok_s = ok ? 1 : 0;
+  }
+  __syncthreads();
+  const bool inv_ok = inv_ok_s != 0;
 
-  for (int64_t g = (int64_t)blockIdx.x * kWaves + wave; g * P < batch; g += (int64_t)gridDim.x * kWaves) {
+  unsigned long long c_rounds = 0, c_solves = 0, c_f1 = 0, c_f2 = 0, c_f3 = 0, c_steps = 0;
+
+  // the next problem's right-hand side and start set are loaded while the
+  // current one is solved
+  const int64_t gstride = (int64_t)gridDim.x * kWaves;
+  int64_t g = (int64_t)blockIdx.x * kWaves + wave;
+  float f_next = 0.0f;
+  uint64_t m_next = 0;
+  {
+    const int64_t b = g * P + sub;
+    if (lane_in && b < batch && p < k) f_next = R[b * ldr + p];
+    if (lane_in && b < batch && mask_in) m_next = mask_in[b];
+  }
+  for (; g * P < batch; g += gstride) {
     const int64_t b = g * P + sub;
     const bool vprob = lane_in && b < batch;
     const bool valid = vprob && p < k;
-    const double f = valid ? (double)R[b * ldr + p] : 0.0;
-    uint64_t F = (vprob && mask_in) ? (mask_in[b] & all & ~pinned0) : 0ull;
+    const double f = (double)f_next;
+    uint64_t F = vprob ? (m_next & all & ~pinned0) : 0ull;
+    {
+      const int64_t bn = (g + gstride) * P + sub;
+      f_next = (lane_in && bn < batch && p < k) ? R[bn * ldr + p] : 0.0f;
+      m_next = (lane_in && bn < batch && mask_in) ? mask_in[bn] : 0ull;
+    }
     uint64_t pinned = pinned0;
     bool warm = F != 0;
     int alpha = 3, beta = k + 1, rounds = 0, since = 0;
     int st = 0;
     bool done = !vprob;
+    bool forceG = false;
     double xfin = 0.0;
+    // unconstrained solution z = G_U^{-1} f
+    double z = 0.0;
+    if (inv_ok) {
+      rfv[wave][lane] = f;
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < K; ++q) z += Gi[q * K + p] * rfv[wave][base + q];
+      wave_lds_sync();
+    }
 
     while (__ballot(!done) != 0) {
       uint64_t Fe = done ? 0ull : F;
+      const uint64_t Ae = done ? 0ull : (all & ~pinned & ~F);
+      const bool useInv = inv_ok && !forceG && __popcll(Ae) < __popcll(Fe);
+      uint64_t Pv = useInv ? Ae : Fe;
+      const double* Mrow = useInv ? Gi : Gs;
       double r[K];
 #pragma unroll
-      for (int q = 0; q < K; ++q) r[q] = Gs[q * K + p];
-      double rf = f, mypiv = 1.0;
+      for (int q = 0; q < K; ++q) r[q] = Mrow[q * K + p];
+      double rf = useInv ? z : f, mypiv = 1.0;
+      bool retry = false;
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const bool pj = (Fe >> j) & 1ull;
+        const bool pj = (Pv >> j) & 1ull;
         if (__ballot(pj) == 0) continue;
         colv[wave][lane] = r[j];
         rfv[wave][lane] = rf;
@@ -99,12 +189,16 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
         const double piv = colv[wave][base + j];
         const double zj = rfv[wave][base + j];
         bool use = pj;
-        if (pj && !(piv > 1e-12 * Gs[j * K + j])) {
+        if (pj && !(piv > 1e-12 * Mrow[j * K + j])) {
           use = false;
-          F &= ~bit64(j);
-          Fe &= ~bit64(j);
-          pinned |= bit64(j);
-          st |= NMF_BPP_SINGULAR;
+          if (useInv) {
+            retry = true;
+          } else {
+            F &= ~bit64(j);
+            Fe &= ~bit64(j);
+            pinned |= bit64(j);
+            st |= NMF_BPP_SINGULAR;
+          }
         }
         const double inv = use ? 1.0 / piv : 0.0;
         const double mlt = (use && p != j) ? r[j] * inv : 0.0;
@@ -115,9 +209,16 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
         wave_lds_sync();
       }
       const bool inF = (Fe >> p) & 1ull;
-      const double x = inF ? rf / mypiv : 0.0;
-      const double y = inF ? 0.0 : -rf;
-      const bool viol = valid && !done && !((pinned >> p) & 1ull) && (inF ? (x < 0.0) : (y < 0.0));
+      const bool isPinned = (pinned >> p) & 1ull;
+      double x, y;
+      if (useInv) {
+        x = inF ? rf : 0.0;
+        y = (inF || isPinned) ? 0.0 : -rf / mypiv;
+      } else {
+        x = inF ? rf / mypiv : 0.0;
+        y = inF ? 0.0 : -rf;
+      }
+      const bool viol = valid && !done && !retry && !isPinned && (inF ? (x < 0.0) : (y < 0.0));
       const uint64_t bal = __ballot(viol);
       uint64_t V;
       if constexpr (K == 64) {
@@ -125,10 +226,12 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
       } else {
         V = (bal >> base) & (bit64(K) - 1ull);
       }
-      if (!done) {
+      if (retry) forceG = true;
+      if (!done && !retry) {
         const unsigned long long nf = (unsigned long long)__popcll(Fe);
         if (p == 0 && lane_in) {
           ++c_rounds;
+          c_steps += (unsigned long long)__popcll(Pv);
           if (nf) {
             ++c_solves;
             c_f1 += nf;
@@ -179,7 +282,7 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
   }
 
   if (counters) {
-    unsigned long long v[NMF_BPP_COUNTERS] = {c_rounds, c_solves, c_f1, c_f2, c_f3};
+    unsigned long long v[NMF_BPP_COUNTERS] = {c_rounds, c_solves, c_f1, c_f2, c_f3, c_steps};
 #pragma unroll
     for (int e = 0; e < NMF_BPP_COUNTERS; ++e) {
       unsigned long long s = v[e];
@@ -203,7 +306,7 @@ int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, f
   constexpr int P = 64 / K;
   const int64_t waves = nmf::cdiv(batch, P);
   int64_t blocks = nmf::cdiv(waves, kWaves);
-  if (blocks > 8192) blocks = 8192;
+  if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(k_bpp<K>, dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
                      mask_out, rounds, status, max_rounds, warm_cap,
                      reinterpret_cast<unsigned long long*>(counters));

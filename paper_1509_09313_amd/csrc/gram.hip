@@ -133,7 +133,7 @@ extern "C" int nmf_gram_workspace_bytes(int64_t rows, int k, size_t* bytes) {
 extern "C" int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* ws, size_t ws_bytes,
                         void* stream) {
   if (!nmf::valid_k(k)) return nmf::fail(NMF_EINVAL, "nmf_gram: k=%d outside [1,64]", k);
-  if (rows < 0 || ldx < k) return nmf::fail(NMF_EINVAL, "nmf_gram: rows=%lld ldx=%lld", (long long)rows, (long long)ldx);
+  if (rows < 0 || (rows > 0 && ldx < k)) return nmf::fail(NMF_EINVAL, "nmf_gram: rows=%lld ldx=%lld", (long long)rows, (long long)ldx);
   if (!G || (rows > 0 && !X)) return nmf::fail(NMF_EINVAL, "nmf_gram: null pointer");
   nmf::Carver c(ws, ws_bytes);
   double* partial;

@@ -13,8 +13,9 @@
 // W2[128][128], b2[128], W3[128][k], b3[k] (input-major).
 //
 // Training is FP32 and deterministic: per-sample activations and their
-// gradients (one block per 8 samples), then every weight gradient as a
-// fixed-order sum over the batch, then Adam.  Inference fuses the features
+// gradients (one block per 8 samples), then all weight gradients as
+// LDS-tiled act^T dact products summed over the batch in sample order, then
+// Adam.  Inference fuses the features
 // and the three layers on v_mfma_f32_16x16x32_bf16: a wavefront takes 16
 // problems, the hidden activations stay in the MFMA accumulators and are
 // fed back as the next layer's B operand (the next layer's weights are staged
@@ -208,47 +209,115 @@ __global__ __launch_bounds__(kH) void k_mlp_act(int k, int batch, int64_t nsamp,
   }
 }
 
-// grad[e] for every parameter e, each a sum over the batch in sample order.
+// Weight and bias gradients as act^T dact products over the batch, one
+// launch for all three layers: the grid is the union of 64 x 64 output tiles
+// of dW1 (2k x 128), dW2 (128 x 128), dW3 (128 x k) plus one row of bias
+// tiles.  Each thread owns a 4 x 4 block and sums the batch in sample order
+// through LDS chunks of 32 samples, so the result is deterministic.
+constexpr int kGT = 64;   // output tile edge
+constexpr int kGB = 32;   // samples per LDS chunk
+constexpr int kGSplit = 128;  // samples per batch split (blockIdx.y); partials summed in split order
+
+struct GradRegion {
+  const float* act;  // nullptr: bias (act = 1)
+  int lda;
+  const float* dact;
+  int ldd;
+  int rows, cols;    // rows = input units (or 1 for a bias), cols = output units
+  int off;           // parameter offset
+};
+
 __global__ __launch_bounds__(256) void k_mlp_wgrad(int k, int batch, const float* __restrict__ xg,
                                                    const float* __restrict__ h1g, const float* __restrict__ h2g,
                                                    const float* __restrict__ dzg, const float* __restrict__ dh1g,
-                                                   const float* __restrict__ dh2g, float* __restrict__ grad) {
+                                                   const float* __restrict__ dh2g, float* __restrict__ gpart) {
   const Layout L = layout(k);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= L.total) return;
-  const float* a;  // activation column (stride sa) or null for a bias
-  const float* g;  // gradient column (stride sg)
-  int sa = 0, sg = 0;
-  if (e < L.b1) {
-    const int i = e / kH, u = e - i * kH;
-    a = xg + i, sa = L.in, g = dh1g + u, sg = kH;
-  } else if (e < L.W2) {
-    a = nullptr, g = dh1g + (e - L.b1), sg = kH;
-  } else if (e < L.b2) {
-    const int v = (e - L.W2) / kH, u = (e - L.W2) - v * kH;
-    a = h1g + v, sa = kH, g = dh2g + u, sg = kH;
-  } else if (e < L.W3) {
-    a = nullptr, g = dh2g + (e - L.b2), sg = kH;
-  } else if (e < L.b3) {
-    const int v = (e - L.W3) / k, c = (e - L.W3) - v * k;
-    a = h2g + v, sa = kH, g = dzg + c, sg = k;
-  } else {
-    a = nullptr, g = dzg + (e - L.b3), sg = k;
+  auto region = [&](int r) -> GradRegion {
+    switch (r) {
+      case 0: return {xg, L.in, dh1g, kH, L.in, kH, L.W1};
+      case 1: return {h1g, kH, dh2g, kH, kH, kH, L.W2};
+      case 2: return {h2g, kH, dzg, k, kH, k, L.W3};
+      case 3: return {nullptr, 0, dh1g, kH, 1, kH, L.b1};
+      case 4: return {nullptr, 0, dh2g, kH, 1, kH, L.b2};
+      default: return {nullptr, 0, dzg, k, 1, k, L.b3};
+    }
+  };
+  // locate this block's tile
+  int tile = blockIdx.x, r = 0;
+  int tr = 0, tc = 0;
+  for (r = 0; r < 6; ++r) {
+    const GradRegion q = region(r);
+    const int nt = ((q.rows + kGT - 1) / kGT) * ((q.cols + kGT - 1) / kGT);
+    if (tile < nt) {
+      const int ntc = (q.cols + kGT - 1) / kGT;
+      tr = tile / ntc;
+      tc = tile - tr * ntc;
+      break;
+    }
+    tile -= nt;
   }
-  float acc = 0.0f;
-  if (a) {
-    for (int b = 0; b < batch; ++b) acc += a[(int64_t)b * sa] * g[(int64_t)b * sg];
-  } else {
-    for (int b = 0; b < batch; ++b) acc += g[(int64_t)b * sg];
+  if (r >= 6) return;
+  const GradRegion g = region(r);
+  __shared__ __align__(16) float as[kGB][kGT];
+  __shared__ __align__(16) float ds[kGB][kGT];
+  const int t = threadIdx.x;
+  const int ti = (t >> 4) * 4, tj = (t & 15) * 4;
+  const int i0 = tr * kGT, j0 = tc * kGT;
+  float acc[4][4] = {};
+  const int bs = blockIdx.y * kGSplit;
+  const int be = (bs + kGSplit < batch) ? bs + kGSplit : batch;
+  float* grad = gpart + (int64_t)blockIdx.y * L.total;
+  for (int b0 = bs; b0 < be; b0 += kGB) {
+    __syncthreads();
+    for (int e = t; e < kGB * kGT; e += 256) {
+      const int bb = e / kGT, c = e - bb * kGT;
+      const int b = b0 + bb;
+      const bool okb = b < be;
+      as[bb][c] = (okb && i0 + c < g.rows) ? (g.act ? g.act[(int64_t)b * g.lda + i0 + c] : 1.0f) : 0.0f;
+      ds[bb][c] = (okb && j0 + c < g.cols) ? g.dact[(int64_t)b * g.ldd + j0 + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int bb = 0; bb < kGB; ++bb) {
+      const float4 av = *reinterpret_cast<const float4*>(&as[bb][ti]);
+      const float4 dv = *reinterpret_cast<const float4*>(&ds[bb][tj]);
+      const float a4[4] = {av.x, av.y, av.z, av.w};
+      const float d4[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += a4[x] * d4[y];
+    }
   }
-  grad[e] = acc;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int i = i0 + ti + x, jj = j0 + tj + y;
+      if (i < g.rows && jj < g.cols) grad[g.off + i * g.cols + jj] = acc[x][y];
+    }
 }
 
-__global__ void k_adam(int n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+int wgrad_blocks(int k) {
+  const Layout L = layout(k);
+  auto nt = [](int r, int c) { return ((r + kGT - 1) / kGT) * ((c + kGT - 1) / kGT); };
+  return nt(L.in, kH) + nt(kH, kH) + nt(kH, k) + nt(1, kH) + nt(1, kH) + nt(1, k);
+}
+
+// grad[e] = sum of the batch-split partials in split order
+__global__ void k_grad_reduce(int n, int S, const float* __restrict__ gpart, float* __restrict__ grad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float s = 0.0f;
+  for (int sp = 0; sp < S; ++sp) s += gpart[(int64_t)sp * n + e];
+  grad[e] = s;
+}
+
+__global__ void k_adam(int n, int S, float* __restrict__ p, const float* __restrict__ gpart, float* __restrict__ m,
                        float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  const float gi = g[e];
+  float gi = 0.0f;
+  for (int sp = 0; sp < S; ++sp) gi += gpart[(int64_t)sp * n + e];
   const float mi = b1 * m[e] + (1.0f - b1) * gi;
   const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
   m[e] = mi;
@@ -290,40 +359,76 @@ union Pack8 {
 __device__ __forceinline__ int chain_unit(int s, int g, int e) { return 32 * s + 16 * (e >> 2) + 4 * g + (e & 3); }
 
 // KS1: 32-wide K-steps of layer 1 (2k <= 32 KS1); NT3: 16-wide output tiles of layer 3.
+// The weights as BF16 A operands, in LDS order: w1 [tile_out 8][kstep KS1][i 16][g 4][8],
+// w2 [8][4][16][4][8], w3 [NT3][4][16][4][8], then the biases b1[128], b2[128], b3[64] (FP32).
+template <int KS1, int NT3>
+struct PackedNet {
+  static constexpr int n1 = 8 * KS1 * 16 * 4 * 8;
+  static constexpr int n2 = 8 * 4 * 16 * 4 * 8;
+  static constexpr int n3 = NT3 * 4 * 16 * 4 * 8;
+  static constexpr int bytes = 2 * (n1 + n2 + n3) + 4 * (kH + kH + 64);
+};
+
+// Builds the packed weights (one thread per entry); used directly by each
+// inference block when no packed copy is supplied.
+template <int KS1, int NT3>
+__device__ inline void pack_entry(int k, const float* __restrict__ p, int e, uint16_t* w, float* bias) {
+  using PN = PackedNet<KS1, NT3>;
+  const Layout L = layout(k);
+  if (e < PN::n1) {
+    const int el = e & 7, gg = (e >> 3) & 3, i = (e >> 5) & 15, s = (e >> 9) % KS1, to = (e >> 9) / KS1;
+    const int in = 32 * s + 8 * gg + el;
+    w[e] = in < L.in ? to_bf16(p[L.W1 + in * kH + 16 * to + i]) : (uint16_t)0;
+  } else if (e < PN::n1 + PN::n2) {
+    const int f = e - PN::n1;
+    const int el = f & 7, gg = (f >> 3) & 3, i = (f >> 5) & 15, s = (f >> 9) & 3, to = f >> 11;
+    w[e] = to_bf16(p[L.W2 + chain_unit(s, gg, el) * kH + 16 * to + i]);
+  } else if (e < PN::n1 + PN::n2 + PN::n3) {
+    const int f = e - PN::n1 - PN::n2;
+    const int el = f & 7, gg = (f >> 3) & 3, i = (f >> 5) & 15, s = (f >> 9) & 3, to = f >> 11;
+    const int c = 16 * to + i;
+    w[e] = c < k ? to_bf16(p[L.W3 + chain_unit(s, gg, el) * k + c]) : (uint16_t)0;
+  } else {
+    const int f = e - PN::n1 - PN::n2 - PN::n3;
+    if (f < kH) bias[f] = p[L.b1 + f];
+    else if (f < 2 * kH) bias[f] = p[L.b2 + f - kH];
+    else if (f < 2 * kH + 64) bias[f] = (f - 2 * kH) < k ? p[L.b3 + f - 2 * kH] : 0.0f;
+  }
+}
+
+template <int KS1, int NT3>
+__global__ void k_mlp_pack(int k, const float* __restrict__ p, uint16_t* __restrict__ packed) {
+  using PN = PackedNet<KS1, NT3>;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < PN::n1 + PN::n2 + PN::n3 + 2 * kH + 64)
+    pack_entry<KS1, NT3>(k, p, e, packed, reinterpret_cast<float*>(packed + PN::n1 + PN::n2 + PN::n3));
+}
+
 template <int KS1, int NT3>
 __global__ __launch_bounds__(256) void k_mlp_infer(int k, int64_t batch, const double* __restrict__ G,
                                                    const float* __restrict__ R, int64_t ldr,
-                                                   const float* __restrict__ p, uint64_t* __restrict__ mask_out) {
+                                                   const float* __restrict__ p, const uint16_t* __restrict__ packed,
+                                                   uint64_t* __restrict__ mask_out) {
+  using PN = PackedNet<KS1, NT3>;
   const Layout L = layout(k);
-  // weights as BF16 A operands: [tile_out][kstep][i (16)][g (4)][8]
-  __shared__ __align__(16) uint16_t w1s[8 * KS1 * 16 * 4 * 8];
-  __shared__ __align__(16) uint16_t w2s[8 * 4 * 16 * 4 * 8];
-  __shared__ __align__(16) uint16_t w3s[NT3 * 4 * 16 * 4 * 8];
-  __shared__ float bias1[kH], bias2[kH], bias3[64];
+  __shared__ __align__(16) uint4 netbuf[(PN::bytes + 15) / 16];
   __shared__ float isd[64], gft[64];
   __shared__ uint64_t pinned_s;
+  uint16_t* w1s = reinterpret_cast<uint16_t*>(netbuf);
+  uint16_t* w2s = w1s + PN::n1;
+  uint16_t* w3s = w2s + PN::n2;
+  float* bias1 = reinterpret_cast<float*>(w3s + PN::n3);
+  float* bias2 = bias1 + kH;
+  float* bias3 = bias2 + kH;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int j = lane & 15, g = lane >> 4;
 
-  for (int e = t; e < 8 * KS1 * 16 * 4 * 8; e += 256) {
-    const int el = e & 7, gg = (e >> 3) & 3, i = (e >> 5) & 15, s = (e >> 9) % KS1, to = (e >> 9) / KS1;
-    const int in = 32 * s + 8 * gg + el;
-    w1s[e] = in < L.in ? to_bf16(p[L.W1 + in * kH + 16 * to + i]) : (uint16_t)0;
+  if (packed) {
+    const uint4* src = reinterpret_cast<const uint4*>(packed);
+    for (int e = t; e < PN::bytes / 16; e += 256) netbuf[e] = src[e];
+  } else {
+    for (int e = t; e < PN::n1 + PN::n2 + PN::n3 + 2 * kH + 64; e += 256) pack_entry<KS1, NT3>(k, p, e, w1s, bias1);
   }
-  for (int e = t; e < 8 * 4 * 16 * 4 * 8; e += 256) {
-    const int el = e & 7, gg = (e >> 3) & 3, i = (e >> 5) & 15, s = (e >> 9) & 3, to = e >> 11;
-    w2s[e] = to_bf16(p[L.W2 + chain_unit(s, gg, el) * kH + 16 * to + i]);
-  }
-  for (int e = t; e < NT3 * 4 * 16 * 4 * 8; e += 256) {
-    const int el = e & 7, gg = (e >> 3) & 3, i = (e >> 5) & 15, s = (e >> 9) & 3, to = e >> 11;
-    const int c = 16 * to + i;
-    w3s[e] = c < k ? to_bf16(p[L.W3 + chain_unit(s, gg, el) * k + c]) : (uint16_t)0;
-  }
-  for (int e = t; e < kH; e += 256) {
-    bias1[e] = p[L.b1 + e];
-    bias2[e] = p[L.b2 + e];
-  }
-  if (t < 64) bias3[t] = t < k ? p[L.b3 + t] : 0.0f;
   if (t == 0) {
     double dmax, mean;
     diag_stats(k, G, &dmax, &mean);
@@ -343,7 +448,23 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int k, int64_t batch, const d
   const uint64_t pinned = pinned_s;
 
   const int64_t ntiles = (batch + 15) / 16;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+  const int64_t tstride = (int64_t)gridDim.x * 4;
+  int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  // raw right-hand sides of the next tile, loaded while the current one runs
+  float rv[KS1][8];
+  auto load_rhs = [&](int64_t tl) {
+    const int64_t bb = tl * 16 + j;
+    const bool okb = tl < ntiles && bb < batch;
+#pragma unroll
+    for (int s = 0; s < KS1; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int in = 32 * s + 8 * g + e;
+        rv[s][e] = (okb && in < k) ? R[bb * ldr + in] : 0.0f;
+      }
+  };
+  load_rhs(tile);
+  for (; tile < ntiles; tile += tstride) {
     const int64_t b = tile * 16 + j;
     const bool ok = b < batch;
     // features of problem b: slot (s, e) of lane group g <-> input 32s + 8g + e
@@ -356,13 +477,14 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int k, int64_t batch, const d
         const int in = 32 * s + 8 * g + e;
         float v = 0.0f;
         if (in < k) {
-          v = ok ? R[b * ldr + in] * isd[in] : 0.0f;
+          v = rv[s][e] * isd[in];
           ss += v * v;
         } else if (in < L.in) {
           v = gft[in - k];
         }
         fv[s][e] = v;
       }
+    load_rhs(tile + tstride);
     __builtin_amdgcn_sched_barrier(0);
     ss += __shfl_xor(ss, 16, 64);
     ss += __shfl_xor(ss, 32, 64);
@@ -448,9 +570,10 @@ struct TrainPlan {
   float* dzg;
   float* dh1g;
   float* dh2g;
-  float* grad;
+  float* gpart;
   double* loss;
   int nblk;
+  int nsplit;
 };
 
 void plan_train(int k, int batch, nmf::Carver& c, TrainPlan* P) {
@@ -462,7 +585,8 @@ void plan_train(int k, int batch, nmf::Carver& c, TrainPlan* P) {
   P->dzg = c.take<float>((size_t)batch * k);
   P->dh1g = c.take<float>((size_t)batch * kH);
   P->dh2g = c.take<float>((size_t)batch * kH);
-  P->grad = c.take<float>((size_t)L.total);
+  P->nsplit = (batch + kGSplit - 1) / kGSplit;
+  P->gpart = c.take<float>((size_t)P->nsplit * L.total);
   P->loss = c.take<double>((size_t)P->nblk);
 }
 
@@ -472,9 +596,8 @@ int grad_step(int k, int batch, int64_t nsamp, int64_t step, int sequential, con
                      masks,
                      P.xg, P.h1g, P.h2g, P.dzg, P.dh1g, P.dh2g, P.loss);
   NMF_TRY(nmf::launch_status("mlp activations"));
-  const int total = layout(k).total;
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3((total + 255) / 256), dim3(256), 0, s, k, batch, P.xg, P.h1g, P.h2g, P.dzg,
-                     P.dh1g, P.dh2g, P.grad);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(wgrad_blocks(k), P.nsplit), dim3(256), 0, s, k, batch, P.xg, P.h1g, P.h2g,
+                     P.dzg, P.dh1g, P.dh2g, P.gpart);
   return nmf::launch_status("mlp weight gradients");
 }
 
@@ -492,30 +615,49 @@ int features_launch(int k, int64_t batch, int64_t stride, const double* G, const
   return launch_status("features");
 }
 
+int packed_bytes(int k) {
+  if (k <= 16) return PackedNet<1, 1>::bytes;
+  if (k <= 32) return PackedNet<2, 2>::bytes;
+  return PackedNet<4, 4>::bytes;
+}
+
 int mlp_infer_plan(int k, int64_t batch, Carver& c, void** scratch) {
-  (void)k;
   (void)batch;
-  (void)c;
-  *scratch = nullptr;
+  *scratch = c.take<uint16_t>((size_t)packed_bytes(k) / 2 + 8);
   return NMF_OK;
 }
 
+// Packs the network's weights into `scratch` (BF16, LDS operand order).
+int mlp_pack_launch(int k, const float* params, void* scratch, hipStream_t s) {
+  uint16_t* out = static_cast<uint16_t*>(scratch);
+  const int n = packed_bytes(k);  // entries <= bytes
+  const dim3 grid((n + 255) / 256);
+  if (k <= 16)
+    hipLaunchKernelGGL((k_mlp_pack<1, 1>), grid, dim3(256), 0, s, k, params, out);
+  else if (k <= 32)
+    hipLaunchKernelGGL((k_mlp_pack<2, 2>), grid, dim3(256), 0, s, k, params, out);
+  else
+    hipLaunchKernelGGL((k_mlp_pack<4, 4>), grid, dim3(256), 0, s, k, params, out);
+  return launch_status("mlp pack");
+}
+
+// scratch: packed weights from mlp_pack_launch, or null to pack per block.
 int mlp_infer_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, const float* params,
                      uint64_t* mask_out, void* scratch, hipStream_t s) {
-  (void)scratch;
   if (batch <= 0) return NMF_OK;
+  const uint16_t* packed = static_cast<const uint16_t*>(scratch);
   const int64_t tiles = cdiv(batch, 16);
   int64_t blocks = cdiv(tiles, 4);
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 512) blocks = 512;
   if (k <= 16)
     hipLaunchKernelGGL((k_mlp_infer<1, 1>), dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, params,
-                       mask_out);
+                       packed, mask_out);
   else if (k <= 32)
     hipLaunchKernelGGL((k_mlp_infer<2, 2>), dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, params,
-                       mask_out);
+                       packed, mask_out);
   else
     hipLaunchKernelGGL((k_mlp_infer<4, 4>), dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, params,
-                       mask_out);
+                       packed, mask_out);
   return launch_status("mlp inference");
 }
 
@@ -557,8 +699,8 @@ extern "C" int nmf_mlp_grad(int k, int batch, const float* params, const float* 
   hipStream_t s = nmf::as_stream(stream);
   NMF_TRY(grad_step(k, batch, batch, 0, 1, nullptr, params, phi, masks, P, s));
   const int total = layout(k).total;
-  const hipError_t e = hipMemcpyAsync(grad_out, P.grad, sizeof(float) * total, hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return nmf::fail(NMF_EHIP, "nmf_mlp_grad: %s", hipGetErrorString(e));
+  hipLaunchKernelGGL(k_grad_reduce, dim3((total + 255) / 256), dim3(256), 0, s, total, P.nsplit, P.gpart, grad_out);
+  NMF_TRY(nmf::launch_status("mlp gradient reduce"));
   if (loss_out) {
     hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, s, P.nblk, P.loss, 1.0 / ((double)batch * k), loss_out);
     NMF_TRY(nmf::launch_status("mlp loss"));
@@ -586,8 +728,8 @@ extern "C" int nmf_mlp_train(int k, float* params, float* adam_m, float* adam_v,
     const double t = (double)(step + 1);
     const float c1 = (float)(1.0 / (1.0 - pow(b1, t)));
     const float c2 = (float)(1.0 / (1.0 - pow(b2, t)));
-    hipLaunchKernelGGL(k_adam, dim3((total + 255) / 256), dim3(256), 0, s, total, params, P.grad, adam_m, adam_v, lr,
-                       (float)b1, (float)b2, 1e-8f, c1, c2);
+    hipLaunchKernelGGL(k_adam, dim3((total + 255) / 256), dim3(256), 0, s, total, P.nsplit, params, P.gpart, adam_m,
+                       adam_v, lr, (float)b1, (float)b2, 1e-8f, c1, c2);
     NMF_TRY(nmf::launch_status("adam"));
   }
   if (loss_out && steps > 0) {

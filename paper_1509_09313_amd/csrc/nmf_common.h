@@ -56,9 +56,8 @@ int gram_launch(int64_t rows, int k, const float* X, int64_t ldx, double* G, dou
                 int nblocks, hipStream_t s);
 
 int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, void** scratch);
-int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda,
-                     const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y,
-                     int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s);
+int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* Bt,
+                     const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s);
 
 int rhs_csr_launch(int64_t rows, int64_t cols, int k, const int64_t* rowptr, const int32_t* colidx,
                    const float* vals, const float* Y, int64_t ldy, float* R, int64_t ldr,
@@ -79,6 +78,20 @@ int dot_f32_launch(int64_t len, const float* a, const float* b, double* out, dou
                    int nblocks, hipStream_t s);
 int dot_f64_launch(int64_t len, const double* a, const double* b, double* out, double* partial,
                    int nblocks, hipStream_t s);
+
+// Kernel-level timing hook: when set (by the ANLS driver), the product
+// launchers record these events right around their main kernel.
+struct KernelMark {
+  hipEvent_t begin = nullptr;
+  hipEvent_t end = nullptr;
+};
+KernelMark& kernel_mark();
+inline void mark_begin(hipStream_t s) {
+  if (kernel_mark().begin) hipEventRecord(kernel_mark().begin, s);
+}
+inline void mark_end(hipStream_t s) {
+  if (kernel_mark().end) hipEventRecord(kernel_mark().end, s);
+}
 
 }  // namespace nmf
 

@@ -17,40 +17,46 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__global__ void k_split(int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx, uint16_t* __restrict__ hi,
-                        uint16_t* __restrict__ lo, int64_t ldo) {
-  const int64_t total = rows * cols;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / cols, c = e - r * cols;
-    const float x = X[r * ldx + c];
-    const uint16_t h = bf16_rne(x);
-    hi[r * ldo + c] = h;
-    lo[r * ldo + c] = bf16_rne(x - bf16_to_f32(h));
-  }
-}
+// Padded BF16 operand: B (rows x cols) as two row-major planes of Rp x Cp
+// BF16 values, Rp = rows rounded up to kTR, Cp = cols rounded up to kTC, zero
+// in the padding: the hi plane, then the lo plane.  Row-major rows keep the 8
+// rows a wavefront loads per instruction spread over memory channels.
+constexpr int kTR = 128;
+constexpr int kTC = 64;
 
-// Transposed split through a 64 x 64 LDS tile: planes of X^T (cols x rows).
-__global__ __launch_bounds__(256) void k_split_t(int64_t rows, int64_t cols, const float* __restrict__ X, int64_t ldx,
-                                                 uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int64_t ldo) {
+// B = X (transpose 0) or X^T (transpose 1); one block per 64 x 64 block of B.
+__global__ __launch_bounds__(256) void k_split_planes(int64_t rows, int64_t cols, const float* __restrict__ X,
+                                                      int64_t ldx, int transpose, int64_t Rp, int64_t Cp,
+                                                      uint16_t* __restrict__ out) {
   __shared__ float tile[64][65];
-  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;  // block origin in B
+  const int64_t brows = transpose ? cols : rows, bcols = transpose ? rows : cols;
+  uint16_t* hi = out;
+  uint16_t* lo = out + Rp * Cp;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t r = r0 + rr, c = c0 + tx;
-    tile[rr][tx] = (r < rows && c < cols) ? X[r * ldx + c] : 0.0f;
-  }
-  __syncthreads();
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t c = c0 + cc, r = r0 + tx;
-    if (c < cols && r < rows) {
-      const float x = tile[tx][cc];
+  if (!transpose) {
+    for (int ii = ty; ii < 64; ii += 4) {
+      const int64_t i = i0 + ii, j = j0 + tx;
+      const float x = (i < brows && j < bcols) ? X[i * ldx + j] : 0.0f;
       const uint16_t h = bf16_rne(x);
-      hi[c * ldo + r] = h;
-      lo[c * ldo + r] = bf16_rne(x - bf16_to_f32(h));
+      hi[i * Cp + j] = h;
+      lo[i * Cp + j] = bf16_rne(x - bf16_to_f32(h));
+    }
+  } else {
+    for (int jj = ty; jj < 64; jj += 4) {  // X row j0 + jj, columns i0 + tx
+      const int64_t j = j0 + jj, i = i0 + tx;
+      tile[jj][tx] = (i < brows && j < bcols) ? X[j * ldx + i] : 0.0f;
+    }
+    __syncthreads();
+    for (int ii = ty; ii < 64; ii += 4) {
+      const int64_t i = i0 + ii, j = j0 + tx;
+      const float x = tile[tx][ii];
+      const uint16_t h = bf16_rne(x);
+      hi[i * Cp + j] = h;
+      lo[i * Cp + j] = bf16_rne(x - bf16_to_f32(h));
     }
   }
 }
-
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
@@ -82,98 +88,82 @@ __global__ __launch_bounds__(256) void k_split_y(int64_t K, int k, int KP, const
   }
 }
 
-constexpr int kBTM = 128;          // rows of B per block (4 waves x 32)
-constexpr int kBTK = 64;           // contraction chunk (BF16 elements)
+constexpr int kBTM = kTR;          // rows of B per block (4 waves x 32)
+constexpr int kBTK = kTC;          // contraction chunk (BF16 elements)
 constexpr int kBPitch = kBTK + 8;  // LDS pitch in uint16 (144 bytes: conflict-free 16-byte reads)
 
-// R (rows x k) = B (rows x K) * Y (K x k) with B and Y given as BF16 planes:
-// D_t[i][j] = R[row0 + 32w + j][32t + i] from three MFMAs per 16-wide K step
-// (Yhi Bhi + Ylo Bhi + Yhi Blo).  blockIdx.y selects a K range (split-K);
-// its partial goes to P + y * split_stride.
-template <int NT, bool VEC>
-__global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int64_t K, int k, const uint16_t* __restrict__ Bh,
-                                                    const uint16_t* __restrict__ Bl, int64_t ldb,
+// R (rows x k) = B (rows x K) * Y (K x k) with B in the padded BF16 form
+// (planes Rp x Cp) and Y as transposed BF16 planes (KP x ldt, ldt = Cp, zero
+// past K): D_t[i][j] = R[row0 + 32w + j][32t + i] from three MFMAs per
+// 16-wide K step (Yhi Bhi + Ylo Bhi + Yhi Blo).  blockIdx.y selects a range
+// of 64-column chunks (split-K); its partial goes to P + y * split_stride.
+template <int NT>
+__global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const uint16_t* __restrict__ B, int64_t Rp,
+                                                    int64_t nkc,
                                                     const uint16_t* __restrict__ Yth, const uint16_t* __restrict__ Ytl,
-                                                    int64_t ldt, float* __restrict__ P, int64_t ldp,
-                                                    int64_t k_per_split, int64_t split_stride) {
+                                                    int64_t ldt, float* __restrict__ P, int64_t ldp, int64_t kc_per_split,
+                                                    int64_t split_stride) {
   constexpr int KP = 32 * NT;
   __shared__ __align__(16) uint16_t Bs[2][kBTM * kBPitch];
   __shared__ __align__(16) uint16_t Ys[2][KP * kBPitch];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j = lane & 31, h = lane >> 5;
   const int64_t row0 = (int64_t)blockIdx.x * kBTM;
-  const int64_t kb = (int64_t)blockIdx.y * k_per_split;
-  const int64_t ke = (kb + k_per_split < K) ? kb + k_per_split : K;
+  const int64_t kc0 = (int64_t)blockIdx.y * kc_per_split;
+  const int64_t kc1 = (kc0 + kc_per_split < nkc) ? kc0 + kc_per_split : nkc;
+  const int64_t Cp = nkc * kTC;
+  const uint16_t* Bh = B + row0 * Cp;
+  const uint16_t* Bl = Bh + Rp * Cp;
 
   v16f acc[NT];
 #pragma unroll
   for (int tt = 0; tt < NT; ++tt) acc[tt] = v16f{};
 
-  uint4 rb[2][4];
-  uint4 ry[2][NT];
-  auto load = [&](int64_t c0) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int q = t + 256 * s;
-      const int rr = q >> 3, c8 = q & 7;
-      const int64_t r = row0 + rr, c = c0 + 8 * c8;
-#pragma unroll
-      for (int pl = 0; pl < 2; ++pl) {
-        const uint16_t* src = (pl ? Bl : Bh) + r * ldb + c;
-        if (VEC && r < rows && c + 7 < ke) {
-          rb[pl][s] = *reinterpret_cast<const uint4*>(src);
-        } else {
-          uint16_t v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (r < rows && c + e < ke) ? src[e] : (uint16_t)0;
-          rb[pl][s] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
-                                 v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < NT; ++s) {
-      const int q = t + 256 * s;
-      const int ii = q >> 3, c8 = q & 7;
-      const int64_t c = c0 + 8 * c8;
-#pragma unroll
-      for (int pl = 0; pl < 2; ++pl) {
-        const uint16_t* src = (pl ? Ytl : Yth) + (int64_t)ii * ldt + c;
-        if (c + 7 < ke) {
-          ry[pl][s] = *reinterpret_cast<const uint4*>(src);
-        } else {
-          uint16_t v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (c + e < ke) ? src[e] : (uint16_t)0;
-          ry[pl][s] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
-                                 v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
-        }
-      }
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int q = t + 256 * s;
-      const int rr = q >> 3, c8 = q & 7;
-#pragma unroll
-      for (int pl = 0; pl < 2; ++pl) *reinterpret_cast<uint4*>(&Bs[pl][rr * kBPitch + 8 * c8]) = rb[pl][s];
-    }
-#pragma unroll
-    for (int s = 0; s < NT; ++s) {
-      const int q = t + 256 * s;
-      const int ii = q >> 3, c8 = q & 7;
-#pragma unroll
-      for (int pl = 0; pl < 2; ++pl) *reinterpret_cast<uint4*>(&Ys[pl][ii * kBPitch + 8 * c8]) = ry[pl][s];
-    }
-  };
-
-  if (kb < ke) load(kb);
-  for (int64_t c0 = kb; c0 < ke; c0 += kBTK) {
+  // staging registers for the next chunk (explicit scalars: no arrays to
+  // keep them out of scratch)
+  uint4 bh0, bh1, bh2, bh3, bl0, bl1, bl2, bl3, yh0, yl0, yh1, yl1;
+#define NMF_LOAD_CHUNK(KC)                                                                  \
+  do {                                                                                      \
+    const int64_t c0_ = (KC) * kTC;                                                         \
+    const uint16_t* ph_ = Bh + (int64_t)(t >> 3) * Cp + c0_ + 8 * (t & 7);                  \
+    const uint16_t* pl_ = ph_ + Rp * Cp;                                                    \
+    const int64_t rs_ = 32 * Cp; /* 256 threads cover 32 rows */                            \
+    bh0 = *reinterpret_cast<const uint4*>(ph_);                                             \
+    bh1 = *reinterpret_cast<const uint4*>(ph_ + rs_);                                       \
+    bh2 = *reinterpret_cast<const uint4*>(ph_ + 2 * rs_);                                   \
+    bh3 = *reinterpret_cast<const uint4*>(ph_ + 3 * rs_);                                   \
+    bl0 = *reinterpret_cast<const uint4*>(pl_);                                             \
+    bl1 = *reinterpret_cast<const uint4*>(pl_ + rs_);                                       \
+    bl2 = *reinterpret_cast<const uint4*>(pl_ + 2 * rs_);                                   \
+    bl3 = *reinterpret_cast<const uint4*>(pl_ + 3 * rs_);                                   \
+    const int64_t yo_ = (int64_t)(t >> 3) * ldt + c0_ + 8 * (t & 7);                        \
+    yh0 = *reinterpret_cast<const uint4*>(Yth + yo_);                                       \
+    yl0 = *reinterpret_cast<const uint4*>(Ytl + yo_);                                       \
+    if (NT == 2) {                                                                          \
+      yh1 = *reinterpret_cast<const uint4*>(Yth + yo_ + 32 * ldt);                          \
+      yl1 = *reinterpret_cast<const uint4*>(Ytl + yo_ + 32 * ldt);                          \
+    }                                                                                       \
+  } while (0)
+  const int so = (t >> 3) * kBPitch + 8 * (t & 7);
+  if (kc0 < kc1) NMF_LOAD_CHUNK(kc0);
+  for (int64_t kc = kc0; kc < kc1; ++kc) {
     __syncthreads();
-    store();
+    *reinterpret_cast<uint4*>(&Bs[0][so]) = bh0;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 32 * kBPitch]) = bh1;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 64 * kBPitch]) = bh2;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 96 * kBPitch]) = bh3;
+    *reinterpret_cast<uint4*>(&Bs[1][so]) = bl0;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 32 * kBPitch]) = bl1;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 64 * kBPitch]) = bl2;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 96 * kBPitch]) = bl3;
+    *reinterpret_cast<uint4*>(&Ys[0][so]) = yh0;
+    *reinterpret_cast<uint4*>(&Ys[1][so]) = yl0;
+    if (NT == 2) {
+      *reinterpret_cast<uint4*>(&Ys[0][so + 32 * kBPitch]) = yh1;
+      *reinterpret_cast<uint4*>(&Ys[1][so + 32 * kBPitch]) = yl1;
+    }
     __syncthreads();
-    if (c0 + kBTK < ke) load(c0 + kBTK);
+    if (kc + 1 < kc1) NMF_LOAD_CHUNK(kc + 1);
 #pragma unroll
     for (int s = 0; s < kBTK / 16; ++s) {
       const int off = 16 * s + 8 * h;
@@ -189,6 +179,7 @@ __global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int64_t K, int
       }
     }
   }
+#undef NMF_LOAD_CHUNK
   float* out = P + (int64_t)blockIdx.y * split_stride;
   const int64_t r = row0 + 32 * w + j;
   if (r < rows) {
@@ -214,9 +205,9 @@ __global__ void k_reduce_splits(int64_t rows, int k, int S, const float* __restr
 }
 
 struct Bf16Plan {
-  int64_t rows, K, ldt;
+  int64_t rows, K, nkc, ldt;
   int KP, S;
-  int64_t kps;
+  int64_t kcps;
 };
 
 Bf16Plan bf16_plan(int side, int64_t m, int64_t n, int k) {
@@ -224,31 +215,27 @@ Bf16Plan bf16_plan(int side, int64_t m, int64_t n, int k) {
   p.rows = side == NMF_SIDE_W ? m : n;
   p.K = side == NMF_SIDE_W ? n : m;
   p.KP = k <= 32 ? 32 : 64;
-  p.ldt = (p.K + 7) / 8 * 8;
+  p.nkc = (p.K + kTC - 1) / kTC;
+  p.ldt = p.nkc * kTC;
   const int64_t tiles = nmf::cdiv(p.rows, kBTM);
   int64_t S = nmf::cdiv(1024, tiles);
-  const int64_t maxS = p.K / 2048 > 1 ? p.K / 2048 : 1;
+  const int64_t maxS = p.nkc / 32 > 1 ? p.nkc / 32 : 1;
   if (S > maxS) S = maxS;
   if (S > 65535) S = 65535;
   if (S < 1) S = 1;
-  int64_t kps = nmf::cdiv(p.K, S);
-  kps = (kps + kBTK - 1) / kBTK * kBTK;
-  if (kps < kBTK) kps = kBTK;
-  p.kps = kps;
-  p.S = (int)nmf::cdiv(p.K, kps);
+  p.kcps = nmf::cdiv(p.nkc, S);
+  p.S = (int)nmf::cdiv(p.nkc, p.kcps);
   if (p.S < 1) p.S = 1;
   return p;
 }
 
-struct Bf16Scratch {
-  uint16_t* yth;
-  uint16_t* ytl;
-  float* partial;
-};
-
 }  // namespace
 
 namespace nmf {
+
+size_t bf16_padded_bytes(int64_t rows, int64_t cols) {
+  return (size_t)2 * (size_t)(cdiv(rows, kTR) * kTR) * (size_t)(cdiv(cols, kTC) * kTC) * sizeof(uint16_t);
+}
 
 int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch) {
   const Bf16Plan p = bf16_plan(side, m, n, k);
@@ -259,8 +246,8 @@ int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch
   return NMF_OK;
 }
 
-int bf16x3_launch(int side, int64_t m, int64_t n, int k, const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb,
-                  const float* Y, int64_t ldy, float* R, int64_t ldr, void* scratch, hipStream_t s) {
+int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const float* Y, int64_t ldy, float* R,
+                  int64_t ldr, void* scratch, hipStream_t s) {
   const Bf16Plan p = bf16_plan(side, m, n, k);
   if (p.rows == 0) return NMF_OK;
   if (p.K == 0) return zero_f32(R, p.rows, k, ldr, s);
@@ -272,20 +259,20 @@ int bf16x3_launch(int side, int64_t m, int64_t n, int k, const uint16_t* B_hi, c
   hipLaunchKernelGGL(k_split_y, dim3((unsigned)cdiv(p.ldt, 64)), dim3(256), 0, s, p.K, k, p.KP, Y, ldy, yth, ytl,
                      p.ldt);
   NMF_TRY(launch_status("rhs bf16x3: split Y"));
-  const bool vec = (ldb % 8 == 0) && ((uintptr_t)B_hi % 16 == 0) && ((uintptr_t)B_lo % 16 == 0);
   float* P = p.S > 1 ? partial : R;
   const int64_t ldp = p.S > 1 ? k : ldr;
   const int64_t stride = p.S > 1 ? p.rows * k : 0;
   const dim3 grid((unsigned)cdiv(p.rows, kBTM), (unsigned)p.S);
-#define NMF_BF16_LAUNCH(NT_, V_)                                                                            \
-  hipLaunchKernelGGL((k_rhs_bf16x3<NT_, V_>), grid, dim3(256), 0, s, p.rows, p.K, k, B_hi, B_lo, ldb, yth, ytl, \
-                     p.ldt, P, ldp, p.kps, stride)
-  if (p.KP == 32) {
-    if (vec) NMF_BF16_LAUNCH(1, true); else NMF_BF16_LAUNCH(1, false);
-  } else {
-    if (vec) NMF_BF16_LAUNCH(2, true); else NMF_BF16_LAUNCH(2, false);
-  }
-#undef NMF_BF16_LAUNCH
+  const uint16_t* B = static_cast<const uint16_t*>(Bt);
+  mark_begin(s);
+  const int64_t Rp = cdiv(p.rows, kBTM) * kBTM;
+  if (p.KP == 32)
+    hipLaunchKernelGGL((k_rhs_bf16x3<1>), grid, dim3(256), 0, s, p.rows, k, B, Rp, p.nkc, yth, ytl, p.ldt, P, ldp,
+                       p.kcps, stride);
+  else
+    hipLaunchKernelGGL((k_rhs_bf16x3<2>), grid, dim3(256), 0, s, p.rows, k, B, Rp, p.nkc, yth, ytl, p.ldt, P, ldp,
+                       p.kcps, stride);
+  mark_end(s);
   NMF_TRY(launch_status("rhs bf16x3"));
   if (p.S > 1) {
     hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)cdiv(p.rows * k, 256)), dim3(256), 0, s, p.rows, k, p.S,
@@ -297,21 +284,20 @@ int bf16x3_launch(int side, int64_t m, int64_t n, int k, const uint16_t* B_hi, c
 
 }  // namespace nmf
 
-extern "C" int nmf_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* hi, uint16_t* lo,
-                              int64_t ldo, int transpose, void* stream) {
+extern "C" size_t nmf_split_bf16_bytes(int64_t rows, int64_t cols, int transpose) {
+  if (rows < 0 || cols < 0) return 0;
+  return transpose ? nmf::bf16_padded_bytes(cols, rows) : nmf::bf16_padded_bytes(rows, cols);
+}
+
+extern "C" int nmf_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, int transpose, void* out,
+                              void* stream) {
   if (rows < 0 || cols < 0 || ldx < cols) return nmf::fail(NMF_EINVAL, "nmf_split_bf16: bad sizes");
-  if (ldo < (transpose ? rows : cols)) return nmf::fail(NMF_EINVAL, "nmf_split_bf16: ldo too small");
-  if (rows * cols > 0 && (!X || !hi || !lo)) return nmf::fail(NMF_EINVAL, "nmf_split_bf16: null pointer");
+  if (rows * cols > 0 && (!X || !out)) return nmf::fail(NMF_EINVAL, "nmf_split_bf16: null pointer");
   if (rows * cols == 0) return NMF_OK;
-  hipStream_t s = nmf::as_stream(stream);
-  if (!transpose) {
-    int64_t blocks = nmf::cdiv(rows * cols, 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_split, dim3((unsigned)blocks), dim3(256), 0, s, rows, cols, X, ldx, hi, lo, ldo);
-  } else {
-    const int64_t gx = nmf::cdiv(cols, 64), gy = nmf::cdiv(rows, 64);
-    if (gy > 65535) return nmf::fail(NMF_EINVAL, "nmf_split_bf16: too many rows");
-    hipLaunchKernelGGL(k_split_t, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, rows, cols, X, ldx, hi, lo, ldo);
-  }
+  const int64_t brows = transpose ? cols : rows, bcols = transpose ? rows : cols;
+  const int64_t Rp = nmf::cdiv(brows, kTR) * kTR, Cp = nmf::cdiv(bcols, kTC) * kTC;
+  if (Rp / 64 > 65535) return nmf::fail(NMF_EINVAL, "nmf_split_bf16: too many rows");
+  hipLaunchKernelGGL(k_split_planes, dim3((unsigned)(Cp / 64), (unsigned)(Rp / 64)), dim3(256), 0,
+                     nmf::as_stream(stream), rows, cols, X, ldx, transpose, Rp, Cp, static_cast<uint16_t*>(out));
   return nmf::launch_status("nmf_split_bf16");
 }

@@ -64,12 +64,14 @@ int rhs_csr_launch(int64_t rows, int64_t cols, int k, const int64_t* rowptr, con
   const int64_t waves = cdiv(rows, rpw);
   int64_t blocks = cdiv(waves, 4);
   if (blocks > 16384) blocks = 16384;
+  mark_begin(s);
   if (k <= 32)
     hipLaunchKernelGGL(k_spmm<32>, dim3((unsigned)blocks), dim3(256), 0, s, rows, k, rowptr, colidx, vals, Y, ldy,
                        R, ldr);
   else
     hipLaunchKernelGGL(k_spmm<64>, dim3((unsigned)blocks), dim3(256), 0, s, rows, k, rowptr, colidx, vals, Y, ldy,
                        R, ldr);
+  mark_end(s);
   return launch_status("rhs csr");
 }
 

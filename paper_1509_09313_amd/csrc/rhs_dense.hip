@@ -14,7 +14,7 @@
 //     16-byte load (a 512-byte contiguous segment per half-wave) and feeds
 //     four MFMAs, one per component; the rows of A are split into S ranges
 //     whose FP32 partials are summed in FP64 in a fixed order.
-// BF16X3 path: see rhs_bf16.hip.
+// BF16X3 path (tiled BF16 operand): see rhs_bf16.hip.
 #include "nmf_common.h"
 
 typedef float v16f __attribute__((ext_vector_type(16)));
@@ -227,10 +227,12 @@ int launch_w_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const
                  float* R, int64_t ldr, hipStream_t s) {
   const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
   const dim3 grid((unsigned)nmf::cdiv(m, kWTM));
+  nmf::mark_begin(s);
   if (vec)
     hipLaunchKernelGGL((k_rhs_w_f32<NT, true>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
   else
     hipLaunchKernelGGL((k_rhs_w_f32<NT, false>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
+  nmf::mark_end(s);
   return nmf::launch_status("rhs side W (fp32)");
 }
 
@@ -243,12 +245,14 @@ int launch_h_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const
   const int64_t ldp = sp.S > 1 ? k : ldr;
   const int64_t stride = sp.S > 1 ? n * k : 0;
   const dim3 grid((unsigned)sp.colgroups, (unsigned)sp.S);
+  nmf::mark_begin(s);
   if (vec)
     hipLaunchKernelGGL((k_rhs_h_f32<NT, true>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
                        sp.rows_per_split, stride);
   else
     hipLaunchKernelGGL((k_rhs_h_f32<NT, false>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
                        sp.rows_per_split, stride);
+  nmf::mark_end(s);
   NMF_TRY(nmf::launch_status("rhs side H (fp32)"));
   if (sp.S > 1) {
     hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)nmf::cdiv(n * k, 256)), dim3(256), 0, s, n, k, sp.S,
@@ -263,9 +267,8 @@ int launch_h_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const
 // BF16X3 entry points (rhs_bf16.hip)
 namespace nmf {
 int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch);
-int bf16x3_launch(int side, int64_t m, int64_t n, int k, const uint16_t* B_hi, const uint16_t* B_lo,
-                  int64_t ldb, const float* Y, int64_t ldy, float* R, int64_t ldr, void* scratch,
-                  hipStream_t s);
+int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const float* Y, int64_t ldy, float* R,
+                  int64_t ldr, void* scratch, hipStream_t s);
 }
 
 namespace nmf {
@@ -280,10 +283,9 @@ int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, v
   return NMF_OK;
 }
 
-int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const uint16_t* B_hi,
-                     const uint16_t* B_lo, int64_t ldb, const float* Y, int64_t ldy, float* R, int64_t ldr,
-                     int prec, void* scratch, hipStream_t s) {
-  if (prec == NMF_BF16X3) return bf16x3_launch(side, m, n, k, B_hi, B_lo, ldb, Y, ldy, R, ldr, scratch, s);
+int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* Bt,
+                     const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s) {
+  if (prec == NMF_BF16X3) return bf16x3_launch(side, m, n, k, Bt, Y, ldy, R, ldr, scratch, s);
   if (side == NMF_SIDE_W) {
     if (m == 0) return NMF_OK;
     return k <= 32 ? launch_w_f32<1>(m, n, k, A, lda, Y, ldy, R, ldr, s)
@@ -297,8 +299,7 @@ int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int6
 }  // namespace nmf
 
 static int check_rhs_args(int side, int64_t m, int64_t n, int k, int prec, const float* A, int64_t lda,
-                          const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y,
-                          int64_t ldy, const float* R, int64_t ldr) {
+                          const void* Bt, const float* Y, int64_t ldy, const float* R, int64_t ldr) {
   if (side != NMF_SIDE_W && side != NMF_SIDE_H) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: bad side %d", side);
   if (prec != NMF_F32 && prec != NMF_BF16X3) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: bad prec %d", prec);
   if (!nmf::valid_k(k)) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: k=%d outside [1,64]", k);
@@ -311,9 +312,7 @@ static int check_rhs_args(int side, int64_t m, int64_t n, int k, int prec, const
     if (lda < n) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: lda < n");
     if (m > 0 && n > 0 && !A) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: A is null");
   } else {
-    const int64_t contracted = side == NMF_SIDE_W ? n : m;
-    if (ldb < contracted) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: ldb too small for the BF16 planes");
-    if (m > 0 && n > 0 && (!B_hi || !B_lo)) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: BF16 planes are null");
+    if (m > 0 && n > 0 && !Bt) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: the tiled BF16 operand is null");
   }
   return NMF_OK;
 }
@@ -330,10 +329,10 @@ extern "C" int nmf_rhs_dense_workspace_bytes(int side, int64_t m, int64_t n, int
   return NMF_OK;
 }
 
-extern "C" int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda,
-                             const uint16_t* B_hi, const uint16_t* B_lo, int64_t ldb, const float* Y, int64_t ldy,
-                             float* R, int64_t ldr, int prec, void* ws, size_t ws_bytes, void* stream) {
-  NMF_TRY(check_rhs_args(side, m, n, k, prec, A, lda, B_hi, B_lo, ldb, Y, ldy, R, ldr));
+extern "C" int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* B_bf16,
+                             const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* ws, size_t ws_bytes,
+                             void* stream) {
+  NMF_TRY(check_rhs_args(side, m, n, k, prec, A, lda, B_bf16, Y, ldy, R, ldr));
   nmf::Carver c(ws, ws_bytes);
   void* scratch;
   NMF_TRY(nmf::rhs_dense_plan(side, m, n, k, prec, c, &scratch));
@@ -342,6 +341,5 @@ extern "C" int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float*
   // an empty contraction gives R = 0
   if (n == 0 && side == NMF_SIDE_W) return nmf::zero_f32(R, m, k, ldr, nmf::as_stream(stream));
   if (m == 0 && side == NMF_SIDE_H) return nmf::zero_f32(R, n, k, ldr, nmf::as_stream(stream));
-  return nmf::rhs_dense_launch(side, m, n, k, A, lda, B_hi, B_lo, ldb, Y, ldy, R, ldr, prec, scratch,
-                               nmf::as_stream(stream));
+  return nmf::rhs_dense_launch(side, m, n, k, A, lda, B_bf16, Y, ldy, R, ldr, prec, scratch, nmf::as_stream(stream));
 }

@@ -56,12 +56,14 @@ def test_host_validation_without_gpu(L):
     assert lib.nnls_bpp_batched(8, 10, G, G, 8, G, 8, None, None, None, None, 0, 8, None, None) == L.NMF_EINVAL
     assert lib.nnls_bpp_batched(8, 10, G, G, 4, G, 8, None, None, None, None, 10, 8, None, None) == L.NMF_EINVAL
     assert lib.nnls_bpp_batched(8, 10, None, G, 8, G, 8, None, None, None, None, 10, 8, None, None) == L.NMF_EINVAL
-    # RHS: bad side, bad prec, lda < n, missing BF16 planes
+    # RHS: bad side, bad prec, lda < n, missing tiled BF16 operand
     z = ctypes.c_void_p(0)
-    assert lib.nmf_rhs_dense(7, 4, 4, 2, G, 4, z, z, 4, G, 2, G, 2, 0, G, 1 << 20, None) == L.NMF_EINVAL
-    assert lib.nmf_rhs_dense(0, 4, 4, 2, G, 4, z, z, 4, G, 2, G, 2, 9, G, 1 << 20, None) == L.NMF_EINVAL
-    assert lib.nmf_rhs_dense(0, 4, 4, 2, G, 3, z, z, 4, G, 2, G, 2, 0, G, 1 << 20, None) == L.NMF_EINVAL
-    assert lib.nmf_rhs_dense(0, 4, 4, 2, z, 4, z, z, 4, G, 2, G, 2, 1, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_rhs_dense(7, 4, 4, 2, G, 4, z, G, 2, G, 2, 0, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_rhs_dense(0, 4, 4, 2, G, 4, z, G, 2, G, 2, 9, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_rhs_dense(0, 4, 4, 2, G, 3, z, G, 2, G, 2, 0, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_rhs_dense(0, 4, 4, 2, z, 4, z, G, 2, G, 2, 1, G, 1 << 20, None) == L.NMF_EINVAL
+    assert lib.nmf_split_bf16_bytes(300, 70, 0) == 2 * 384 * 128 * 2
+    assert lib.nmf_split_bf16_bytes(300, 70, 1) == 2 * 128 * 320 * 2
     # CSR: ld < k
     assert lib.nmf_rhs_csr(4, 4, 8, G, G, G, G, 4, G, 8, None) == L.NMF_EINVAL
     # objective and ANLS: null matrix / bad opts

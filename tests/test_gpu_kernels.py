@@ -262,20 +262,20 @@ def test_rhs_dense_bf16x3(m, n, k, pad):
     Ht = rng.uniform(0.0, 1.0, (n, k)).astype(np.float32)
     W = rng.uniform(0.0, 1.0, (m, k)).astype(np.float32)
     Ad = padded(A, pad)
-    hi, lo = L.nmf_split_bf16(Ad)
-    hit, lot = L.nmf_split_bf16(Ad, transpose=True)
+    bt = L.nmf_split_bf16(Ad)
+    btt = L.nmf_split_bf16(Ad, transpose=True)
     hb, lb = osplit.split_bits(A)
-    assert np.array_equal(hi.cpu().numpy().view(np.uint16), hb)
-    assert np.array_equal(lo.cpu().numpy().view(np.uint16), lb)
-    assert np.array_equal(hit.cpu().numpy().view(np.uint16), hb.T)
-    assert np.array_equal(lot.cpu().numpy().view(np.uint16), lb.T)
+    hi, lo = L.unpack_bf16(bt, m, n)
+    assert np.array_equal(hi, hb) and np.array_equal(lo, lb)
+    hit, lot = L.unpack_bf16(btt, n, m)
+    assert np.array_equal(hit, hb.T) and np.array_equal(lot, lb.T)
     A64 = np.abs(A.astype(np.float64))
-    Rw = L.nmf_rhs_dense(L.NMF_SIDE_W, None, cuda(Ht), prec=L.NMF_BF16X3, B_hi=hi, B_lo=lo, m=m, n=n)
+    Rw = L.nmf_rhs_dense(L.NMF_SIDE_W, None, cuda(Ht), prec=L.NMF_BF16X3, B_bf16=bt, m=m, n=n)
     Rwo = osplit.rhs_w(A, Ht)
     bw = 1.01 * 3 * n * U32 * (A64 @ np.abs(Ht.astype(np.float64)))
     err = np.abs(Rw.cpu().numpy().astype(np.float64) - Rwo)
     assert np.all(err <= bw), np.max(err / bw)
-    Rh = L.nmf_rhs_dense(L.NMF_SIDE_H, None, cuda(W), prec=L.NMF_BF16X3, B_hi=hit, B_lo=lot, m=m, n=n)
+    Rh = L.nmf_rhs_dense(L.NMF_SIDE_H, None, cuda(W), prec=L.NMF_BF16X3, B_bf16=btt, m=m, n=n)
     Rho = osplit.rhs_h(A, W)
     bh = 1.01 * 3 * (m + 1) * U32 * (A64.T @ np.abs(W.astype(np.float64)))
     err = np.abs(Rh.cpu().numpy().astype(np.float64) - Rho)
