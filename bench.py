@@ -213,18 +213,27 @@ def roofline(bench, timers_l, stats_l):
         with open(TRAFFIC) as fh:
             tr = json.load(fh)
         ent = tr.get(dom)
-        if ent and ent.get("source_sha256") == source_digest():
+        if ent and ent.get("source_sha256") == source_digest(dom):
             out["traffic"] = ent["bytes_per_launch"]
     except (OSError, ValueError):
         pass
     return out
 
 
-def source_digest():
+# sources that define each phase's kernels; counter results are tied to them
+PHASE_SOURCES = {
+    "rhs_w": ("rhs_bf16.hip", "nmf_common.h"), "rhs_h": ("rhs_bf16.hip", "nmf_common.h"),
+    "bpp_w": ("bpp.hip", "nmf_common.h"), "bpp_h": ("bpp.hip", "nmf_common.h"),
+    "gram_w": ("gram.hip", "nmf_common.h"), "gram_h": ("gram.hip", "nmf_common.h"),
+    "infer_w": ("mlp.hip", "nmf_common.h"), "infer_h": ("mlp.hip", "nmf_common.h"),
+}
+
+
+def source_digest(phase):
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1509_09313_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in PHASE_SOURCES[phase]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -281,7 +290,7 @@ def pmc_mode(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (this build runs on a single MI355X)",
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     if a.pmc:

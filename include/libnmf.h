@@ -38,7 +38,7 @@ extern "C" {
 /* ---- status codes --------------------------------------------------------- */
 #define NMF_OK 0
 #define NMF_EINVAL 1        /* bad size, leading dimension, null pointer, k */
-#define NMF_EUNSUPPORTED 2  /* a combination this build does not implement */
+#define NMF_EUNSUPPORTED 2  /* a combination the library does not implement */
 #define NMF_EHIP 3          /* a HIP runtime call or kernel launch failed */
 #define NMF_EWORKSPACE 4    /* ws too small (query *_workspace_bytes) */
 

@@ -97,7 +97,9 @@ constexpr int kBPitch = kBTK + 8;  // LDS pitch in uint16 (144 bytes: conflict-f
 // past K): D_t[i][j] = R[row0 + 32w + j][32t + i] from three MFMAs per
 // 16-wide K step (Yhi Bhi + Ylo Bhi + Yhi Blo).  blockIdx.y selects a range
 // of 64-column chunks (split-K); its partial goes to P + y * split_stride.
-template <int NT>
+// SIDE (NMF_SIDE_W / NMF_SIDE_H) does not change the code; it only gives the
+// two products distinct kernel names in traces.
+template <int NT, int SIDE>
 __global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const uint16_t* __restrict__ B, int64_t Rp,
                                                     int64_t nkc,
                                                     const uint16_t* __restrict__ Yth, const uint16_t* __restrict__ Ytl,
@@ -266,12 +268,9 @@ int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const f
   const uint16_t* B = static_cast<const uint16_t*>(Bt);
   mark_begin(s);
   const int64_t Rp = cdiv(p.rows, kBTM) * kBTM;
-  if (p.KP == 32)
-    hipLaunchKernelGGL((k_rhs_bf16x3<1>), grid, dim3(256), 0, s, p.rows, k, B, Rp, p.nkc, yth, ytl, p.ldt, P, ldp,
-                       p.kcps, stride);
-  else
-    hipLaunchKernelGGL((k_rhs_bf16x3<2>), grid, dim3(256), 0, s, p.rows, k, B, Rp, p.nkc, yth, ytl, p.ldt, P, ldp,
-                       p.kcps, stride);
+  auto kern = side == NMF_SIDE_W ? (p.KP == 32 ? k_rhs_bf16x3<1, NMF_SIDE_W> : k_rhs_bf16x3<2, NMF_SIDE_W>)
+                                  : (p.KP == 32 ? k_rhs_bf16x3<1, NMF_SIDE_H> : k_rhs_bf16x3<2, NMF_SIDE_H>);
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, p.rows, k, B, Rp, p.nkc, yth, ytl, p.ldt, P, ldp, p.kcps, stride);
   mark_end(s);
   NMF_TRY(launch_status("rhs bf16x3"));
   if (p.S > 1) {
