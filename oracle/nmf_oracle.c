@@ -22,7 +22,7 @@
  *   - the KKT conditions (Eq. KKT) used as the acceptance test of each BPP
  *     round.
  *
- * Readings where the paper is silent (see the design notes):
+ * Readings where the paper is silent (the same rules hold on the GPU path):
  *   - index i is "pinned" (kept at x_i = 0, never made passive) when
  *     G_ii <= 1e-14 * max_l G_ll, or when its Cholesky pivot on the passive
  *     subset is <= 1e-12 * G_ii;

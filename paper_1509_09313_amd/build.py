@@ -23,7 +23,8 @@ ARCH = os.environ.get("NMF_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC,
-    # packed FP32 VALU ops stay off (see the design notes)
+    # packed FP32 VALU ops stay off: the compiler forms them from plain float code and some of their
+    # forms have given wrong results without an error on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]

@@ -1,7 +1,7 @@
 """Per-kernel parity of libnmf (through the C-ABI) against the FP64 CPU oracle
 on identical seeded inputs, including ragged shapes and degenerate cases.
 
-Tolerances come from the arithmetic (derivations in the design notes):
+Tolerances come from the arithmetic of each kernel:
   Gram   FP64 sums of exact FP32 products: |dG| <= rows * 2^-52 * |X|^T|X|
   RHS    FP32 accumulation over L terms:   |dR| <= L * 2^-24 * |A||Y|
   SpMM   FP64 sums in the oracle's order, then one rounding: bit-identical
