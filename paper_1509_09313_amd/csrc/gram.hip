@@ -11,11 +11,20 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTileRows = 128;
-constexpr int kMaxBlocks = 512;
+constexpr int kTileRows = 64;
+constexpr int kMaxBlocks = 1024;
 
+// Partials are stored entry-major, partial[e * nblocks + block], so that the
+// reduction reads each entry's partials contiguously.  KW (32 or 64) lanes
+// load one row of a tile: thread t loads column t % KW of rows t / KW + step
+// * (256 / KW), so every load of a tile has its address from one base and a
+// stride; the next tile is loaded into registers while the current one is
+// used.
+template <int KW>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, const float* __restrict__ X,
                                                            int64_t ldx, double* __restrict__ partial) {
+  constexpr int kRowsPerPass = kThreads / KW;
+  constexpr int kLoads = kTileRows / kRowsPerPass;
   __shared__ float tile[kTileRows][64 + 4];
   __shared__ double red[kThreads * 4];  // slice reduction scratch (re-used)
   const int kp = (k + 3) & ~3;
@@ -30,21 +39,39 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, 
   int bi = 0, rem = pair;
   while (rem >= kt - bi) { rem -= kt - bi; ++bi; }
   const int bj = bi + rem;
+  const int lc = t % KW, lr = t / KW;
+  const bool col_ok = lc < k;
 
   double acc[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = 0.0;
 
+  float stage[kLoads];
   const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
-  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+  int64_t tl = blockIdx.x;
+  if (tl < ntiles) {
+    const int64_t rb = tl * kTileRows + lr;
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int64_t r = rb + u * kRowsPerPass;
+      stage[u] = (col_ok && r < rows) ? X[r * ldx + lc] : 0.0f;
+    }
+  }
+  for (; tl < ntiles; tl += gridDim.x) {
     const int64_t r0 = tl * kTileRows;
     __syncthreads();
-    for (int idx = t; idx < kTileRows * kp; idx += kThreads) {
-      const int rr = idx / kp, cc = idx - rr * kp;
-      const int64_t r = r0 + rr;
-      tile[rr][cc] = (r < rows && cc < k) ? X[r * ldx + cc] : 0.0f;
-    }
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) tile[lr + u * kRowsPerPass][lc] = stage[u];
     __syncthreads();
+    const int64_t tn = tl + gridDim.x;
+    if (tn < ntiles) {
+      const int64_t rb = tn * kTileRows + lr;
+#pragma unroll
+      for (int u = 0; u < kLoads; ++u) {
+        const int64_t r = rb + u * kRowsPerPass;
+        stage[u] = (col_ok && r < rows) ? X[r * ldx + lc] : 0.0f;
+      }
+    }
     if (active) {
       const int nr = (int)((rows - r0) < kTileRows ? (rows - r0) : kTileRows);
       for (int rr = slice; rr < nr; rr += slices) {
@@ -60,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, 
     }
   }
   // combine slices in order, four entries of the 4 x 4 block at a time
-  double* out = partial + (int64_t)blockIdx.x * k * k;
+  const int64_t nb = gridDim.x;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     __syncthreads();
@@ -79,20 +106,26 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, 
       for (int e = 0; e < 4; ++e) {
         const int gi = 4 * bi + ii, gj = 4 * bj + e;
         if (gi < k && gj < k) {
-          out[gi * k + gj] = s[e];
-          out[gj * k + gi] = s[e];
+          partial[(int64_t)(gi * k + gj) * nb + blockIdx.x] = s[e];
+          partial[(int64_t)(gj * k + gi) * nb + blockIdx.x] = s[e];
         }
       }
     }
   }
 }
 
-__global__ void k_gram_reduce(int k, int nblocks, const double* __restrict__ partial, double* __restrict__ G) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per entry of G: lane l sums partials l, l + 64, ... in order,
+// then the 64 lane sums are combined by a fixed butterfly.
+__global__ __launch_bounds__(256) void k_gram_reduce(int k, int nblocks, const double* __restrict__ partial,
+                                                     double* __restrict__ G) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (e >= k * k) return;
+  const double* p = partial + (int64_t)e * nblocks;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * k * k + e];
-  G[e] = s;
+  for (int b = lane; b < nblocks; b += 64) s += p[b];
+  s = wave_sum_f64(s);
+  if (lane == 0) G[e] = s;
 }
 
 int gram_blocks(int64_t rows) {
@@ -112,9 +145,12 @@ int gram_plan(int64_t rows, int k, Carver& c, double** partial, int* nblocks) {
 
 int gram_launch(int64_t rows, int k, const float* X, int64_t ldx, double* G, double* partial, int nblocks,
                 hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_partial, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial);
+  if (k <= 32)
+    hipLaunchKernelGGL(k_gram_partial<32>, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial);
+  else
+    hipLaunchKernelGGL(k_gram_partial<64>, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial);
   NMF_TRY(launch_status("gram partial"));
-  hipLaunchKernelGGL(k_gram_reduce, dim3((k * k + 255) / 256), dim3(256), 0, s, k, nblocks, partial, G);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((k * k + 3) / 4), dim3(256), 0, s, k, nblocks, partial, G);
   return launch_status("gram reduce");
 }
 

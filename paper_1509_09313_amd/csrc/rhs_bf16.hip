@@ -5,6 +5,8 @@
 // accumulation: the lo*lo term (relative size 2^-16 per operand pair) is
 // dropped.  Bytes per entry of A stay 4 (two BF16 planes), so the product is
 // HBM-bound where the FP32 MFMA form is compute-bound.
+#include <atomic>
+
 #include "nmf_common.h"
 
 namespace {
@@ -95,8 +97,13 @@ constexpr int kBPitch = kBTK + 8;  // LDS pitch in uint16 (144 bytes: conflict-f
 // R (rows x k) = B (rows x K) * Y (K x k) with B in the padded BF16 form
 // (planes Rp x Cp) and Y as transposed BF16 planes (KP x ldt, ldt = Cp, zero
 // past K): D_t[i][j] = R[row0 + 32w + j][32t + i] from three MFMAs per
-// 16-wide K step (Yhi Bhi + Ylo Bhi + Yhi Blo).  blockIdx.y selects a range
+// 16-wide K step (Yhi Bhi + Ylo Bhi + Yhi Blo).  The K index of a tile selects a range
 // of 64-column chunks (split-K); its partial goes to P + y * split_stride.
+// The grid is one-dimensional and XCD-aware: workgroups are dispatched to the
+// 8 XCDs round-robin, so launch index L runs on XCD L % 8; L is remapped to
+// the logical tile (L % 8) * (grid / 8) + L / 8, which gives every XCD a
+// contiguous range of logical tiles, row tile fastest.  All row tiles of one
+// K-range then run on the same XCD and share that range of Y in its L2.
 // SIDE (NMF_SIDE_W / NMF_SIDE_H) does not change the code; it only gives the
 // two products distinct kernel names in traces.
 template <int NT, int SIDE>
@@ -104,14 +111,18 @@ __global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const u
                                                     int64_t nkc,
                                                     const uint16_t* __restrict__ Yth, const uint16_t* __restrict__ Ytl,
                                                     int64_t ldt, float* __restrict__ P, int64_t ldp, int64_t kc_per_split,
-                                                    int64_t split_stride) {
+                                                    int64_t split_stride, int64_t ntiles, int64_t nsplit) {
   constexpr int KP = 32 * NT;
+  const int64_t per_xcd = gridDim.x / 8;
+  const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (lid >= ntiles * nsplit) return;
+  const int64_t bx = lid % ntiles, by = lid / ntiles;
   __shared__ __align__(16) uint16_t Bs[2][kBTM * kBPitch];
   __shared__ __align__(16) uint16_t Ys[2][KP * kBPitch];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j = lane & 31, h = lane >> 5;
-  const int64_t row0 = (int64_t)blockIdx.x * kBTM;
-  const int64_t kc0 = (int64_t)blockIdx.y * kc_per_split;
+  const int64_t row0 = bx * kBTM;
+  const int64_t kc0 = by * kc_per_split;
   const int64_t kc1 = (kc0 + kc_per_split < nkc) ? kc0 + kc_per_split : nkc;
   const int64_t Cp = nkc * kTC;
   const uint16_t* Bh = B + row0 * Cp;
@@ -182,7 +193,7 @@ __global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const u
     }
   }
 #undef NMF_LOAD_CHUNK
-  float* out = P + (int64_t)blockIdx.y * split_stride;
+  float* out = P + by * split_stride;
   const int64_t r = row0 + 32 * w + j;
   if (r < rows) {
 #pragma unroll
@@ -212,7 +223,42 @@ struct Bf16Plan {
   int64_t kcps;
 };
 
-Bf16Plan bf16_plan(int side, int64_t m, int64_t n, int k) {
+// Workgroups of the product kernel that fit on the device at once (all CUs),
+// from the occupancy calculator; 0 if it cannot be queried.  Cached per
+// device and per K width.
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_capacity[kMaxDevices][2];
+
+int bf16_capacity(int KP) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+  const int which = KP == 32 ? 0 : 1;
+  int cap = g_capacity[dev][which].load(std::memory_order_relaxed);
+  if (cap > 0) return cap;
+  int per_cu = 0, cus = 0;
+  const hipError_t e1 = which == 0
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rhs_bf16x3<1, NMF_SIDE_H>, 256, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rhs_bf16x3<2, NMF_SIDE_H>, 256, 0);
+  const hipError_t e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e1 != hipSuccess || e2 != hipSuccess || per_cu <= 0 || cus <= 0) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  cap = per_cu * cus;
+  g_capacity[dev][which].store(cap, std::memory_order_relaxed);
+  return cap;
+}
+
+// Workspace is sized for at most kMaxBlocksSized concurrent workgroups, so
+// the split count used at launch (from the device's capacity) never exceeds
+// the one the workspace was sized for.
+constexpr int64_t kMaxBlocksSized = 4096;
+
+// capacity <= 0: sizing for the workspace (upper bound of the split count).
+// Otherwise the split count makes rows-tiles x splits fit the device at once
+// (no partial second wave of workgroups) when there are fewer row tiles than
+// resident workgroups.
+Bf16Plan bf16_plan(int side, int64_t m, int64_t n, int k, int capacity) {
   Bf16Plan p;
   p.rows = side == NMF_SIDE_W ? m : n;
   p.K = side == NMF_SIDE_W ? n : m;
@@ -220,7 +266,8 @@ Bf16Plan bf16_plan(int side, int64_t m, int64_t n, int k) {
   p.nkc = (p.K + kTC - 1) / kTC;
   p.ldt = p.nkc * kTC;
   const int64_t tiles = nmf::cdiv(p.rows, kBTM);
-  int64_t S = nmf::cdiv(1024, tiles);
+  const int64_t cap = capacity > 0 && capacity < kMaxBlocksSized ? capacity : kMaxBlocksSized;
+  int64_t S = cap / (tiles > 0 ? tiles : 1);
   const int64_t maxS = p.nkc / 32 > 1 ? p.nkc / 32 : 1;
   if (S > maxS) S = maxS;
   if (S > 65535) S = 65535;
@@ -240,7 +287,7 @@ size_t bf16_padded_bytes(int64_t rows, int64_t cols) {
 }
 
 int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch) {
-  const Bf16Plan p = bf16_plan(side, m, n, k);
+  const Bf16Plan p = bf16_plan(side, m, n, k, 0);
   // the scratch block starts with the two Y planes, then the split partials
   uint16_t* y = c.take<uint16_t>((size_t)2 * p.KP * p.ldt);
   if (p.S > 1) c.take<float>((size_t)p.S * p.rows * k);
@@ -250,7 +297,8 @@ int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch
 
 int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const float* Y, int64_t ldy, float* R,
                   int64_t ldr, void* scratch, hipStream_t s) {
-  const Bf16Plan p = bf16_plan(side, m, n, k);
+  const int KP = k <= 32 ? 32 : 64;
+  const Bf16Plan p = bf16_plan(side, m, n, k, bf16_capacity(KP));
   if (p.rows == 0) return NMF_OK;
   if (p.K == 0) return zero_f32(R, p.rows, k, ldr, s);
   uint16_t* yth = static_cast<uint16_t*>(scratch);
@@ -264,13 +312,15 @@ int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const f
   float* P = p.S > 1 ? partial : R;
   const int64_t ldp = p.S > 1 ? k : ldr;
   const int64_t stride = p.S > 1 ? p.rows * k : 0;
-  const dim3 grid((unsigned)cdiv(p.rows, kBTM), (unsigned)p.S);
+  const int64_t ntiles = cdiv(p.rows, kBTM);
+  const dim3 grid((unsigned)(cdiv(ntiles * p.S, 8) * 8));
   const uint16_t* B = static_cast<const uint16_t*>(Bt);
   mark_begin(s);
   const int64_t Rp = cdiv(p.rows, kBTM) * kBTM;
   auto kern = side == NMF_SIDE_W ? (p.KP == 32 ? k_rhs_bf16x3<1, NMF_SIDE_W> : k_rhs_bf16x3<2, NMF_SIDE_W>)
                                   : (p.KP == 32 ? k_rhs_bf16x3<1, NMF_SIDE_H> : k_rhs_bf16x3<2, NMF_SIDE_H>);
-  hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, p.rows, k, B, Rp, p.nkc, yth, ytl, p.ldt, P, ldp, p.kcps, stride);
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, p.rows, k, B, Rp, p.nkc, yth, ytl, p.ldt, P, ldp, p.kcps, stride,
+                     ntiles, (int64_t)p.S);
   mark_end(s);
   NMF_TRY(launch_status("rhs bf16x3"));
   if (p.S > 1) {
