@@ -44,6 +44,7 @@
 namespace {
 
 constexpr int kWaves = 4;
+constexpr int kSmall = 4;  // pivot-set size handled by the small-system path
 
 __device__ __forceinline__ uint64_t bit64(int i) { return 1ull << i; }
 
@@ -174,50 +175,161 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
       const bool useInv = inv_ok && !forceG && __popcll(Ae) < __popcll(Fe);
       uint64_t Pv = useInv ? Ae : Fe;
       const double* Mrow = useInv ? Gi : Gs;
-      double r[K];
-#pragma unroll
-      for (int q = 0; q < K; ++q) r[q] = Mrow[q * K + p];
-      double rf = useInv ? z : f, mypiv = 1.0;
+      const double rf0 = useInv ? z : f;
       bool retry = false;
+      double x, y;
+      if (__ballot(__popcll(Pv) > kSmall) == 0) {
+        // Small pivot sets (every problem of the wavefront): each lane reads
+        // the entries it needs, M[p][j] for the pivots j, and solves the
+        // s x s system M_PP u = rhs_P redundantly by LDL^T in index order
+        // (the same pivots and pivot tests as the elimination below).
+        int jj[kSmall];
+        bool vt[kSmall];
+        uint64_t rem = Pv;
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const bool pj = (Pv >> j) & 1ull;
-        if (__ballot(pj) == 0) continue;
-        colv[wave][lane] = r[j];
-        rfv[wave][lane] = rf;
+        for (int t = 0; t < kSmall; ++t) {
+          vt[t] = rem != 0ull;
+          jj[t] = rem != 0ull ? (__ffsll((unsigned long long)rem) - 1) : 0;
+          rem &= rem - 1ull;
+        }
+        rfv[wave][lane] = rf0;
         wave_lds_sync();
-        const double piv = colv[wave][base + j];
-        const double zj = rfv[wave][base + j];
-        bool use = pj;
-        if (pj && !(piv > 1e-12 * Mrow[j * K + j])) {
-          use = false;
-          if (useInv) {
-            retry = true;
-          } else {
-            F &= ~bit64(j);
-            Fe &= ~bit64(j);
-            pinned |= bit64(j);
-            st |= NMF_BPP_SINGULAR;
+        double bt[kSmall], mc[kSmall], dg[kSmall];
+#pragma unroll
+        for (int t = 0; t < kSmall; ++t) {
+          bt[t] = vt[t] ? rfv[wave][base + jj[t]] : 0.0;
+          mc[t] = vt[t] ? Mrow[jj[t] * K + p] : 0.0;
+          dg[t] = vt[t] ? Mrow[jj[t] * K + jj[t]] : 1.0;
+        }
+        wave_lds_sync();
+        // the largest pivot set of the wavefront bounds the (uniform) steps
+        int smax = 0;
+#pragma unroll
+        for (int t = 0; t < kSmall; ++t)
+          if (__ballot(vt[t]) != 0) smax = t + 1;
+        double Lm[kSmall][kSmall], rinv[kSmall], dd[kSmall], u[kSmall];
+#pragma unroll
+        for (int a = 0; a < kSmall; ++a) {
+#pragma unroll
+          for (int b = 0; b < kSmall; ++b) Lm[b][a] = 0.0;
+          rinv[a] = 0.0;
+          dd[a] = 0.0;
+          u[a] = 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < kSmall; ++a) {
+          if (a < smax) {
+            double col[kSmall];
+#pragma unroll
+            for (int b = a; b < kSmall; ++b) {
+              double v = 0.0;
+              if (b < smax) {
+                v = (vt[a] && vt[b]) ? Mrow[jj[b] * K + jj[a]] : 0.0;
+#pragma unroll
+                for (int c = 0; c < a; ++c) v -= Lm[b][c] * Lm[a][c] * dd[c];
+              }
+              col[b] = v;
+            }
+            const bool ok = vt[a] && col[a] > 1e-12 * dg[a];
+            if (vt[a] && !ok) {
+              if (useInv) {
+                retry = true;
+              } else {
+                const uint64_t bj = bit64(jj[a]);
+                F &= ~bj;
+                Fe &= ~bj;
+                pinned |= bj;
+                st |= NMF_BPP_SINGULAR;
+              }
+              vt[a] = false;
+            }
+            const double ra = ok ? 1.0 / col[a] : 0.0;
+            rinv[a] = ra;
+            dd[a] = ok ? col[a] : 0.0;
+#pragma unroll
+            for (int b = a + 1; b < kSmall; ++b) Lm[b][a] = col[b] * ra;
           }
         }
-        const double inv = use ? 1.0 / piv : 0.0;
-        const double mlt = (use && p != j) ? r[j] * inv : 0.0;
-        if (use && p == j) mypiv = piv;
+        // L w = rhs, then u = D^-1 w - L^T u (back)
 #pragma unroll
-        for (int q = j + 1; q < K; ++q) r[q] -= mlt * colv[wave][base + q];
-        rf -= mlt * zj;
-        wave_lds_sync();
-      }
-      const bool inF = (Fe >> p) & 1ull;
-      const bool isPinned = (pinned >> p) & 1ull;
-      double x, y;
-      if (useInv) {
-        x = inF ? rf : 0.0;
-        y = (inF || isPinned) ? 0.0 : -rf / mypiv;
+        for (int a = 0; a < kSmall; ++a) {
+          if (a < smax) {
+            double v = vt[a] ? bt[a] : 0.0;
+#pragma unroll
+            for (int c = 0; c < a; ++c) v -= Lm[a][c] * u[c];
+            u[a] = v;
+          }
+        }
+#pragma unroll
+        for (int a = kSmall - 1; a >= 0; --a) {
+          if (a < smax) {
+            double v = u[a] * rinv[a];
+#pragma unroll
+            for (int b = a + 1; b < kSmall; ++b) v -= Lm[b][a] * u[b];
+            u[a] = vt[a] ? v : 0.0;
+          }
+        }
+        double own = 0.0, corr = 0.0;
+#pragma unroll
+        for (int t = 0; t < kSmall; ++t) {
+          if (vt[t] && jj[t] == p) own = u[t];
+          corr += mc[t] * u[t];
+        }
+        const bool inF = (Fe >> p) & 1ull;
+        const bool isPinned = (pinned >> p) & 1ull;
+        if (useInv) {
+          x = inF ? z - corr : 0.0;
+          y = (inF || isPinned) ? 0.0 : -own;
+        } else {
+          x = inF ? own : 0.0;
+          y = inF ? 0.0 : corr - f;
+        }
       } else {
-        x = inF ? rf / mypiv : 0.0;
-        y = inF ? 0.0 : -rf;
+        double r[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) r[q] = Mrow[q * K + p];
+        double rf = rf0, mypiv = 1.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const bool pj = (Pv >> j) & 1ull;
+          if (__ballot(pj) == 0) continue;
+          colv[wave][lane] = r[j];
+          rfv[wave][lane] = rf;
+          wave_lds_sync();
+          const double piv = colv[wave][base + j];
+          const double zj = rfv[wave][base + j];
+          bool use = pj;
+          if (pj && !(piv > 1e-12 * Mrow[j * K + j])) {
+            use = false;
+            if (useInv) {
+              retry = true;
+            } else {
+              F &= ~bit64(j);
+              Fe &= ~bit64(j);
+              pinned |= bit64(j);
+              st |= NMF_BPP_SINGULAR;
+            }
+          }
+          const double inv = use ? 1.0 / piv : 0.0;
+          const double mlt = (use && p != j) ? r[j] * inv : 0.0;
+          if (use && p == j) mypiv = piv;
+#pragma unroll
+          for (int q = j + 1; q < K; ++q) r[q] -= mlt * colv[wave][base + q];
+          rf -= mlt * zj;
+          wave_lds_sync();
+        }
+        const bool inF = (Fe >> p) & 1ull;
+        const bool isPinned = (pinned >> p) & 1ull;
+        if (useInv) {
+          x = inF ? rf : 0.0;
+          y = (inF || isPinned) ? 0.0 : -rf / mypiv;
+        } else {
+          x = inF ? rf / mypiv : 0.0;
+          y = inF ? 0.0 : -rf;
+        }
       }
+      const bool isPinned = (pinned >> p) & 1ull;
+      const bool inF = (Fe >> p) & 1ull;
       const bool viol = valid && !done && !retry && !isPinned && (inF ? (x < 0.0) : (y < 0.0));
       const uint64_t bal = __ballot(viol);
       uint64_t V;
