@@ -286,6 +286,85 @@ int nmf_anls_workspace_bytes(const nmf_matrix* A, int k, const nmf_opts* o, size
 int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, int iters, const nmf_opts* o,
                   nmf_iter_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- many uneven instances: grouped persistent phases, graphs, tuning ------
+ * Algorithm 1 run on a batch of independent dense NMF problems of different
+ * m, n and k (each as nmf_anls_iter with NMF_BF16X3 right-hand sides, FP64
+ * Gram matrices and FP64 BPP from cold starts).  Every phase of an iteration
+ * is one persistent launch that walks a work list spanning all instances
+ * (Gram tiles, Y splits, BF16x3 product tiles with split-K, split sums and
+ * ranges of NNLS problems), so an iteration is a fixed sequence of launches
+ * whatever the batch size, and a whole run can be captured as one graph.
+ *
+ * Problem i: A_i (m x n) is given by its padded BF16 planes in both
+ * orientations (nmf_split_bf16 with transpose 0 and 1); W_i (m x k, ld ldw)
+ * is overwritten; Ht_i (n x k, ld ldh) holds the initial H^T and receives
+ * the result.  All pointers are device pointers owned by the caller. */
+typedef struct nmf_batch_problem {
+  int64_t m, n;
+  int k, pad;
+  const void* A_bf16;   /* nmf_split_bf16(m, n, A, lda, 0, ...) */
+  const void* At_bf16;  /* nmf_split_bf16(m, n, A, lda, 1, ...) */
+  float* W;
+  int64_t ldw;
+  float* Ht;
+  int64_t ldh;
+} nmf_batch_problem;
+
+/* Work-item sizes of the grouped phases (what the autotuner chooses). */
+typedef struct nmf_batch_tune {
+  int gram_tiles;    /* 64-row tiles per Gram work item (>= 1) */
+  int rhs_w_chunks;  /* 64-column chunks of the contraction per A H^T item (>= 1; split-K) */
+  int rhs_h_chunks;  /* 64-row chunks of the contraction per A^T W item (>= 1; split-K) */
+  int bpp_problems;  /* NNLS problems per BPP item (>= 64) */
+  int grid_scale;    /* persistent grid = grid_scale x resident workgroups (1..8) */
+  int warm_prev;     /* 1: each NNLS starts from its own passive set of the previous
+                      * iteration (kept in the workspace; cold after a reset, and a
+                      * warm start still unsolved after 8 rounds restarts cold);
+                      * the solutions are the same either way.  Not searched by the
+                      * autotuner, which keeps the default (1). */
+} nmf_batch_tune;
+
+#define NMF_BATCH_RESET 1  /* flag: clear the kept passive sets first (cold start) */
+
+/* Fills a tuning that works everywhere (used when tune is NULL below). */
+void nmf_batch_tune_default(nmf_batch_tune* t);
+
+/* Workspace for a plan with tuning t; t == NULL gives a size that fits every
+ * tuning nmf_batch_autotune tries (and the default). */
+int nmf_batch_workspace_bytes(int count, const nmf_batch_problem* P, const nmf_batch_tune* t, size_t* bytes);
+
+/* Lays out the per-instance buffers and builds the work lists in ws
+ * (synchronous: the lists are copied to the device before it returns).  The
+ * plan is a host object; ws and the problems' buffers must outlive it.
+ * Errors: NMF_EINVAL (count < 1, a bad size or k, a null pointer),
+ * NMF_EWORKSPACE, NMF_EHIP. */
+int nmf_batch_plan_create(int count, const nmf_batch_problem* P, const nmf_batch_tune* t, void* ws,
+                          size_t ws_bytes, void** plan);
+int nmf_batch_plan_destroy(void* plan);
+
+/* Enqueues `iters` iterations (W update then H update of every instance) on
+ * stream; no host synchronisation and no allocation, so it may be captured.
+ * flags: NMF_BATCH_RESET clears the kept passive sets first (with a fill
+ * kernel).  counters: optional device array of 2 * NMF_BPP_COUNTERS uint64
+ * (W side, then H side), added to (not cleared). */
+int nmf_batch_iterate(void* plan, int iters, uint64_t* counters, int flags, void* stream);
+
+/* Captures nmf_batch_iterate(plan, iters, counters, flags) on `stream` (a
+ * non-null stream) into an executable graph; launch it any number of times
+ * (with NMF_BATCH_RESET every launch starts cold). */
+int nmf_batch_graph_create(void* plan, int iters, uint64_t* counters, int flags, void* stream, void** graph);
+int nmf_batch_graph_launch(void* graph, void* stream);
+int nmf_batch_graph_destroy(void* graph);
+
+/* Chooses the work-item sizes by timing one iteration per candidate
+ * (coordinate search over each field in turn, starting from the default).
+ * The problems' W and Ht are saved to the workspace first and restored
+ * afterwards, so the batch is left as it was.  ws must hold
+ * nmf_batch_workspace_bytes(count, P, NULL).  best_ms: time of one iteration
+ * with the chosen tuning (optional). */
+int nmf_batch_autotune(int count, const nmf_batch_problem* P, void* ws, size_t ws_bytes, nmf_batch_tune* best,
+                       double* best_ms, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,7 @@ NMF_OBJ_DIRECT, NMF_OBJ_TRACE = 0, 1
 NMF_WARM_COLD, NMF_WARM_PREV, NMF_WARM_LEARNED = 0, 1, 2
 NMF_BPP_WARM_FALLBACK, NMF_BPP_CAPPED, NMF_BPP_PINNED, NMF_BPP_SINGULAR = 1, 2, 4, 8
 NMF_BPP_COUNTERS = 6
+NMF_BATCH_RESET = 1
 PHASES = ("rhs_w", "infer_w", "bpp_w", "gram_w", "rhs_h", "infer_h", "bpp_h", "gram_h", "other")
 NMF_PHASES = len(PHASES)
 
@@ -65,6 +66,19 @@ class nmf_iter_stats(ctypes.Structure):
 
 STATS_WORDS = ctypes.sizeof(nmf_iter_stats) // 8
 
+
+class nmf_batch_problem(ctypes.Structure):
+    _fields_ = [("m", i64), ("n", i64), ("k", ci), ("pad", ci), ("A_bf16", vp), ("At_bf16", vp),
+                ("W", vp), ("ldw", i64), ("Ht", vp), ("ldh", i64)]
+
+
+class nmf_batch_tune(ctypes.Structure):
+    _fields_ = [("gram_tiles", ci), ("rhs_w_chunks", ci), ("rhs_h_chunks", ci), ("bpp_problems", ci),
+                ("grid_scale", ci), ("warm_prev", ci)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
 _lib = None
 
 
@@ -77,6 +91,8 @@ def lib():
         sz = ctypes.POINTER(ctypes.c_size_t)
         M = ctypes.POINTER(nmf_matrix)
         O = ctypes.POINTER(nmf_opts)
+        BP = ctypes.POINTER(nmf_batch_problem)
+        BT = ctypes.POINTER(nmf_batch_tune)
         sig = {
             "nmf_last_error": ([], ctypes.c_char_p),
             "nmf_version": ([], ctypes.c_char_p),
@@ -104,11 +120,21 @@ def lib():
             "nmf_mlp_grad": ([ci, ci, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ci),
             "nmf_mlp_train": ([ci, vp, vp, vp, vp, vp, i64, vp, ci, ci, ctypes.c_float, i64, vp, vp,
                                ctypes.c_size_t, vp], ci),
+            "nmf_batch_workspace_bytes": ([ci, BP, BT, sz], ci),
+            "nmf_batch_plan_create": ([ci, BP, BT, vp, ctypes.c_size_t, ctypes.POINTER(vp)], ci),
+            "nmf_batch_plan_destroy": ([vp], ci),
+            "nmf_batch_iterate": ([vp, ci, vp, ci, vp], ci),
+            "nmf_batch_graph_create": ([vp, ci, vp, ci, vp, ctypes.POINTER(vp)], ci),
+            "nmf_batch_graph_launch": ([vp, vp], ci),
+            "nmf_batch_graph_destroy": ([vp], ci),
+            "nmf_batch_autotune": ([ci, BP, vp, ctypes.c_size_t, BT, ctypes.POINTER(ctypes.c_double), vp], ci),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        L.nmf_batch_tune_default.argtypes = [BT]
+        L.nmf_batch_tune_default.restype = None
         _lib = L
     return _lib
 
@@ -431,3 +457,97 @@ class PhaseTimer:
         if self.events is not None:
             lib().nmf_events_destroy(self.n, self.events)
             self.events = None
+
+
+# ---------------------------------------------------------------- batches ----
+def batch_tune_default() -> nmf_batch_tune:
+    t = nmf_batch_tune()
+    lib().nmf_batch_tune_default(ctypes.byref(t))
+    return t
+
+
+class Batch:
+    """Many independent dense NMF problems run together by the grouped,
+    persistent phase kernels of libnmf (nmf_batch_*).
+
+    problems: list of dicts with keys A (m x n float32, CUDA), W (m x k),
+    Ht (n x k).  The padded BF16 planes of A in both orientations are made
+    here (nmf_split_bf16) and kept alive with the tensors."""
+
+    def __init__(self, problems, tune=None):
+        self.items = []
+        P = (nmf_batch_problem * len(problems))()
+        for i, pr in enumerate(problems):
+            A, W, Ht = pr["A"], pr["W"], pr["Ht"]
+            _dev(A, torch.float32, "A")
+            _dev(W, torch.float32, "W")
+            _dev(Ht, torch.float32, "Ht")
+            m, n = A.shape
+            k = W.shape[1]
+            bt = nmf_split_bf16(A)
+            btt = nmf_split_bf16(A, transpose=True)
+            self.items.append((A, W, Ht, bt, btt))
+            P[i] = nmf_batch_problem(m, n, k, 0, bt.data_ptr(), btt.data_ptr(), W.data_ptr(), _ld(W),
+                                     Ht.data_ptr(), _ld(Ht))
+        self.P = P
+        self.count = len(problems)
+        nb = ctypes.c_size_t(0)
+        _check(lib().nmf_batch_workspace_bytes(self.count, P, None, ctypes.byref(nb)))
+        self.ws = _ws(nb.value)
+        self.plan = None
+        self.graphs = []
+        self.tune = None
+        self.make_plan(tune)
+
+    def make_plan(self, tune=None):
+        if self.plan is not None:
+            _check(lib().nmf_batch_plan_destroy(self.plan))
+            self.plan = None
+        torch.cuda.synchronize()
+        h = vp()
+        t = ctypes.byref(tune) if tune is not None else None
+        _check(lib().nmf_batch_plan_create(self.count, self.P, t, _ptr(self.ws), self.ws.numel(), ctypes.byref(h)))
+        self.plan = h
+        self.tune = tune if tune is not None else batch_tune_default()
+        self.fresh = True   # the kept passive sets are uninitialised until a reset
+
+    def autotune(self):
+        best = nmf_batch_tune()
+        ms = ctypes.c_double(0.0)
+        _check(lib().nmf_batch_autotune(self.count, self.P, _ptr(self.ws), self.ws.numel(), ctypes.byref(best),
+                                        ctypes.byref(ms), _stream()))
+        self.make_plan(best)
+        return best, ms.value
+
+    def iterate(self, iters, counters=None, reset=False):
+        """Enqueues `iters` iterations; reset (or a new plan) starts every NNLS cold."""
+        flags = NMF_BATCH_RESET if (reset or self.fresh) else 0
+        _check(lib().nmf_batch_iterate(self.plan, int(iters), _ptr(counters), flags, _stream()))
+        self.fresh = False
+
+    def graph(self, iters, counters=None, reset=True):
+        """Captures `iters` iterations on the current (non-default) stream;
+        with reset every launch starts cold."""
+        g = vp()
+        flags = NMF_BATCH_RESET if reset else 0
+        _check(lib().nmf_batch_graph_create(self.plan, int(iters), _ptr(counters), flags, _stream(),
+                                            ctypes.byref(g)))
+        self.graphs.append(g)
+        return g
+
+    def launch(self, g):
+        _check(lib().nmf_batch_graph_launch(g, _stream()))
+
+    def close(self):
+        for g in self.graphs:
+            lib().nmf_batch_graph_destroy(g)
+        self.graphs = []
+        if self.plan is not None:
+            lib().nmf_batch_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

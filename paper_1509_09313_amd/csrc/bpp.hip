@@ -39,6 +39,7 @@
 // from the start; a passive-subset pivot <= 1e-12 G_jj pins its index
 // (removed from F, never made passive again).  Pinned indices are excluded
 // from V.  These rules match the CPU reference.
+#include "batched.h"
 #include "nmf_common.h"
 
 namespace {
@@ -48,20 +49,24 @@ constexpr int kSmall = 4;  // pivot-set size handled by the small-system path
 
 __device__ __forceinline__ uint64_t bit64(int i) { return 1ull << i; }
 
+// Solves problems b0 + g * P + sub (g = g_first, g_first + g_step, ... while
+// b0 + g * P < b1) of one Gram matrix G; P = 64 / K problems per wavefront,
+// sub selects the lane group.  Loads G into LDS first (after a barrier, so a
+// persistent loop may call it again with another G).  Round and solve
+// statistics are added to cacc (per lane; summed by the caller).
 template <int K>
-__global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double* __restrict__ G,
-                                             const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
-                                             int64_t ldx, const uint64_t* mask_in,
-                                             uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
-                                             uint8_t* __restrict__ status_out, int max_rounds, int warm_cap,
-                                             unsigned long long* __restrict__ counters) {
+__device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, const float* __restrict__ R,
+                                          int64_t ldr, float* __restrict__ X, int64_t ldx, const uint64_t* mask_in,
+                                          uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
+                                          uint8_t* __restrict__ status_out, int max_rounds, int warm_cap, int64_t b0,
+                                          int64_t b1, int64_t g_first, int64_t g_step,
+                                          unsigned long long (&cacc)[NMF_BPP_COUNTERS]) {
   constexpr int P = 64 / K;
   __shared__ double Gs[K * K];
   __shared__ double Gi[K * K];
   __shared__ int inv_ok_s;
   __shared__ double colv[kWaves][64];
   __shared__ double rfv[kWaves][64];
-  __shared__ unsigned long long cnt[kWaves][NMF_BPP_COUNTERS];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool lane_in = lane < P * K;
@@ -69,6 +74,7 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
   const int p = lane_in ? lane % K : 0;
   const int base = sub * K;
 
+  __syncthreads();
   for (int idx = t; idx < K * K; idx += 256) {
     const int q = idx / K, pp = idx - q * K;
     Gs[idx] = (q < k && pp < k) ? G[q * k + pp] : (q == pp ? 1.0 : 0.0);
@@ -93,6 +99,7 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
 #pragma unroll
     for (int q = 0; q < K; ++q) r[q] = Gs[q * K + pl];
     bool ok = true;
+#pragma unroll 1
     for (int j = 0; j < K; ++j) {
       const bool sweep = j < k && !((pinned0 >> j) & 1ull);
       if (sweep) {
@@ -132,25 +139,25 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
 
   // the next problem's right-hand side and start set are loaded while the
   // current one is solved
-  const int64_t gstride = (int64_t)gridDim.x * kWaves;
-  int64_t g = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t gstride = g_step;
+  int64_t g = g_first;
   float f_next = 0.0f;
   uint64_t m_next = 0;
   {
-    const int64_t b = g * P + sub;
-    if (lane_in && b < batch && p < k) f_next = R[b * ldr + p];
-    if (lane_in && b < batch && mask_in) m_next = mask_in[b];
+    const int64_t b = b0 + g * P + sub;
+    if (lane_in && b < b1 && p < k) f_next = R[b * ldr + p];
+    if (lane_in && b < b1 && mask_in) m_next = mask_in[b];
   }
-  for (; g * P < batch; g += gstride) {
-    const int64_t b = g * P + sub;
-    const bool vprob = lane_in && b < batch;
+  for (; b0 + g * P < b1; g += gstride) {
+    const int64_t b = b0 + g * P + sub;
+    const bool vprob = lane_in && b < b1;
     const bool valid = vprob && p < k;
     const double f = (double)f_next;
     uint64_t F = vprob ? (m_next & all & ~pinned0) : 0ull;
     {
-      const int64_t bn = (g + gstride) * P + sub;
-      f_next = (lane_in && bn < batch && p < k) ? R[bn * ldr + p] : 0.0f;
-      m_next = (lane_in && bn < batch && mask_in) ? mask_in[bn] : 0ull;
+      const int64_t bn = b0 + (g + gstride) * P + sub;
+      f_next = (lane_in && bn < b1 && p < k) ? R[bn * ldr + p] : 0.0f;
+      m_next = (lane_in && bn < b1 && mask_in) ? mask_in[bn] : 0ull;
     }
     uint64_t pinned = pinned0;
     bool warm = F != 0;
@@ -289,34 +296,36 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
 #pragma unroll
         for (int q = 0; q < K; ++q) r[q] = Mrow[q * K + p];
         double rf = rf0, mypiv = 1.0;
+        {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const bool pj = (Pv >> j) & 1ull;
-          if (__ballot(pj) == 0) continue;
-          colv[wave][lane] = r[j];
-          rfv[wave][lane] = rf;
-          wave_lds_sync();
-          const double piv = colv[wave][base + j];
-          const double zj = rfv[wave][base + j];
-          bool use = pj;
-          if (pj && !(piv > 1e-12 * Mrow[j * K + j])) {
-            use = false;
-            if (useInv) {
-              retry = true;
-            } else {
-              F &= ~bit64(j);
-              Fe &= ~bit64(j);
-              pinned |= bit64(j);
-              st |= NMF_BPP_SINGULAR;
+          for (int j = 0; j < K; ++j) {
+            const bool pj = (Pv >> j) & 1ull;
+            if (__ballot(pj) == 0) continue;
+            colv[wave][lane] = r[j];
+            rfv[wave][lane] = rf;
+            wave_lds_sync();
+            const double piv = colv[wave][base + j];
+            const double zj = rfv[wave][base + j];
+            bool use = pj;
+            if (pj && !(piv > 1e-12 * Mrow[j * K + j])) {
+              use = false;
+              if (useInv) {
+                retry = true;
+              } else {
+                F &= ~bit64(j);
+                Fe &= ~bit64(j);
+                pinned |= bit64(j);
+                st |= NMF_BPP_SINGULAR;
+              }
             }
-          }
-          const double inv = use ? 1.0 / piv : 0.0;
-          const double mlt = (use && p != j) ? r[j] * inv : 0.0;
-          if (use && p == j) mypiv = piv;
+            const double inv = use ? 1.0 / piv : 0.0;
+            const double mlt = (use && p != j) ? r[j] * inv : 0.0;
+            if (use && p == j) mypiv = piv;
 #pragma unroll
-          for (int q = j + 1; q < K; ++q) r[q] -= mlt * colv[wave][base + q];
-          rf -= mlt * zj;
-          wave_lds_sync();
+            for (int q = j + 1; q < K; ++q) r[q] -= mlt * colv[wave][base + q];
+            rf -= mlt * zj;
+            wave_lds_sync();
+          }
         }
         const bool inF = (Fe >> p) & 1ull;
         const bool isPinned = (pinned >> p) & 1ull;
@@ -393,22 +402,63 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
     }
   }
 
-  if (counters) {
-    unsigned long long v[NMF_BPP_COUNTERS] = {c_rounds, c_solves, c_f1, c_f2, c_f3, c_steps};
+  cacc[0] += c_rounds;
+  cacc[1] += c_solves;
+  cacc[2] += c_f1;
+  cacc[3] += c_f2;
+  cacc[4] += c_f3;
+  cacc[5] += c_steps;
+}
+
+// Sums the per-lane statistics of the block and adds them to counters.
+__device__ __forceinline__ void flush_counters(const unsigned long long (&cacc)[NMF_BPP_COUNTERS],
+                                               unsigned long long* __restrict__ counters) {
+  __shared__ unsigned long long cnt[kWaves][NMF_BPP_COUNTERS];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
-    for (int e = 0; e < NMF_BPP_COUNTERS; ++e) {
-      unsigned long long s = v[e];
+  for (int e = 0; e < NMF_BPP_COUNTERS; ++e) {
+    unsigned long long s = cacc[e];
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-      if (lane == 0) cnt[wave][e] = s;
-    }
-    __syncthreads();
-    if (t < NMF_BPP_COUNTERS) {
-      unsigned long long s = 0;
-      for (int w = 0; w < kWaves; ++w) s += cnt[w][t];
-      if (s) atomicAdd(counters + t, s);
-    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) cnt[wave][e] = s;
   }
+  __syncthreads();
+  if (t < NMF_BPP_COUNTERS) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kWaves; ++w) s += cnt[w][t];
+    if (s) atomicAdd(counters + t, s);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double* __restrict__ G,
+                                             const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
+                                             int64_t ldx, const uint64_t* mask_in,
+                                             uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
+                                             uint8_t* __restrict__ status_out, int max_rounds, int warm_cap,
+                                             unsigned long long* __restrict__ counters) {
+  unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
+  const int wave = threadIdx.x >> 6;
+  bpp_block<K>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0, batch,
+               (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves, cacc);
+  if (counters) flush_counters(cacc, counters);
+}
+
+// Grouped form: a persistent walk over items, each a range of problems of
+// one Gram matrix (start sets from, and final sets to, the item's masks when
+// it has them; cold starts otherwise).
+template <int K>
+__global__ __launch_bounds__(256) void k_bpp_grouped(const nmf::BppItem* __restrict__ items, int64_t n,
+                                                     int max_rounds, int warm_cap,
+                                                     unsigned long long* __restrict__ counters) {
+  unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
+  const int wave = threadIdx.x >> 6;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::BppItem it = items[i];
+    bpp_block<K>(it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status, max_rounds, warm_cap,
+                 it.b0, it.b1, wave, kWaves, cacc);
+  }
+  if (counters) flush_counters(cacc, counters);
 }
 
 template <int K>
@@ -438,6 +488,36 @@ int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ld
   if (k <= 32) return launch<32>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
   if (k <= 56) return launch<56>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
   return launch<64>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
+}
+
+int bpp_grouped_launch(int K, const BppItem* items, int64_t n, int grid, int max_rounds, int warm_cap,
+                       uint64_t* counters, hipStream_t s) {
+  if (n == 0) return NMF_OK;
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(counters);
+  switch (K) {
+    case 8: hipLaunchKernelGGL(k_bpp_grouped<8>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
+    case 16: hipLaunchKernelGGL(k_bpp_grouped<16>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
+    case 32: hipLaunchKernelGGL(k_bpp_grouped<32>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
+    case 56: hipLaunchKernelGGL(k_bpp_grouped<56>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
+    case 64: hipLaunchKernelGGL(k_bpp_grouped<64>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
+    default: return fail(NMF_EINVAL, "bpp (grouped): K=%d", K);
+  }
+  return launch_status("nnls bpp (grouped)");
+}
+
+int bpp_class(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k <= 56 ? 56 : 64; }
+
+int bpp_grouped_occupancy(int K, int* per_cu) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (K) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<8>, 256, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<16>, 256, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<32>, 256, 0); break;
+    case 56: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<56>, 256, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<64>, 256, 0); break;
+    default: break;
+  }
+  return e == hipSuccess ? NMF_OK : NMF_EHIP;
 }
 
 }  // namespace nmf

@@ -6,6 +6,7 @@
 // thread accumulates a 4 x 4 block of the upper triangle of G for one slice of
 // the tile's rows; slices and then blocks are combined in a fixed order, so
 // the FP64 result does not depend on scheduling.
+#include "batched.h"
 #include "nmf_common.h"
 
 namespace {
@@ -14,15 +15,17 @@ constexpr int kThreads = 256;
 constexpr int kTileRows = 64;
 constexpr int kMaxBlocks = 1024;
 
-// Partials are stored entry-major, partial[e * nblocks + block], so that the
-// reduction reads each entry's partials contiguously.  KW (32 or 64) lanes
-// load one row of a tile: thread t loads column t % KW of rows t / KW + step
-// * (256 / KW), so every load of a tile has its address from one base and a
-// stride; the next tile is loaded into registers while the current one is
-// used.
+// Sums X[t*64 .. t*64+64)^T X[...] over the 64-row tiles t = t_begin,
+// t_begin + t_step, ... < t_end into out[e * out_stride] (both triangles,
+// e = i * k + j).  KW (32 or 64) lanes load one row of a tile: thread t loads
+// column t % KW of rows t / KW + step * (256 / KW), so every load of a tile
+// has its address from one base and a stride; the next tile is loaded into
+// registers while the current one is used.  Starts and ends with a barrier-
+// safe use of its LDS, so a persistent loop may call it repeatedly.
 template <int KW>
-__global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, const float* __restrict__ X,
-                                                           int64_t ldx, double* __restrict__ partial) {
+__device__ __forceinline__ void gram_tiles(int64_t rows, int k, const float* __restrict__ X, int64_t ldx,
+                                           int64_t t_begin, int64_t t_end, int64_t t_step, double* __restrict__ out,
+                                           int64_t out_stride) {
   constexpr int kRowsPerPass = kThreads / KW;
   constexpr int kLoads = kTileRows / kRowsPerPass;
   __shared__ float tile[kTileRows][64 + 4];
@@ -47,9 +50,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, 
   for (int e = 0; e < 16; ++e) acc[e] = 0.0;
 
   float stage[kLoads];
-  const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
-  int64_t tl = blockIdx.x;
-  if (tl < ntiles) {
+  int64_t tl = t_begin;
+  if (tl < t_end) {
     const int64_t rb = tl * kTileRows + lr;
 #pragma unroll
     for (int u = 0; u < kLoads; ++u) {
@@ -57,14 +59,14 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, 
       stage[u] = (col_ok && r < rows) ? X[r * ldx + lc] : 0.0f;
     }
   }
-  for (; tl < ntiles; tl += gridDim.x) {
+  for (; tl < t_end; tl += t_step) {
     const int64_t r0 = tl * kTileRows;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kLoads; ++u) tile[lr + u * kRowsPerPass][lc] = stage[u];
     __syncthreads();
-    const int64_t tn = tl + gridDim.x;
-    if (tn < ntiles) {
+    const int64_t tn = tl + t_step;
+    if (tn < t_end) {
       const int64_t rb = tn * kTileRows + lr;
 #pragma unroll
       for (int u = 0; u < kLoads; ++u) {
@@ -87,7 +89,6 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, 
     }
   }
   // combine slices in order, four entries of the 4 x 4 block at a time
-  const int64_t nb = gridDim.x;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     __syncthreads();
@@ -106,10 +107,43 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, 
       for (int e = 0; e < 4; ++e) {
         const int gi = 4 * bi + ii, gj = 4 * bj + e;
         if (gi < k && gj < k) {
-          partial[(int64_t)(gi * k + gj) * nb + blockIdx.x] = s[e];
-          partial[(int64_t)(gj * k + gi) * nb + blockIdx.x] = s[e];
+          out[(int64_t)(gi * k + gj) * out_stride] = s[e];
+          out[(int64_t)(gj * k + gi) * out_stride] = s[e];
         }
       }
+    }
+  }
+  __syncthreads();
+}
+
+// Partials are stored entry-major, partial[e * nblocks + block], so that the
+// reduction reads each entry's partials contiguously.
+template <int KW>
+__global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, const float* __restrict__ X,
+                                                           int64_t ldx, double* __restrict__ partial) {
+  const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
+  gram_tiles<KW>(rows, k, X, ldx, blockIdx.x, ntiles, gridDim.x, partial + blockIdx.x, gridDim.x);
+}
+
+// Grouped form: item i sums its own tile range into its own k x k partial.
+__global__ __launch_bounds__(kThreads) void k_gram_grouped(const nmf::GramItem* __restrict__ items, int64_t n) {
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::GramItem it = items[i];
+    gram_tiles<64>(it.rows, it.k, it.X, it.ldx, it.tile0, it.tile0 + it.ntiles, 1, it.partial, 1);
+  }
+}
+
+// Grouped reduction: G[e] = sum over the instance's item partials in order.
+__global__ __launch_bounds__(256) void k_gram_reduce_grouped(const nmf::GramReduceItem* __restrict__ items,
+                                                             int64_t n) {
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::GramReduceItem it = items[i];
+    const int64_t e = it.e0 + threadIdx.x;
+    const int64_t kk = (int64_t)it.k * it.k;
+    if (e < kk) {
+      double s = 0.0;
+      for (int sl = 0; sl < it.nslots; ++sl) s += it.partial[sl * kk + e];
+      it.G[e] = s;
     }
   }
 }
@@ -152,6 +186,24 @@ int gram_launch(int64_t rows, int k, const float* X, int64_t ldx, double* G, dou
   NMF_TRY(launch_status("gram partial"));
   hipLaunchKernelGGL(k_gram_reduce, dim3((k * k + 3) / 4), dim3(256), 0, s, k, nblocks, partial, G);
   return launch_status("gram reduce");
+}
+
+int gram_grouped_launch(const GramItem* items, int64_t n, int grid, hipStream_t s) {
+  if (n == 0) return NMF_OK;
+  hipLaunchKernelGGL(k_gram_grouped, dim3((unsigned)grid), dim3(kThreads), 0, s, items, n);
+  return launch_status("gram (grouped)");
+}
+
+int gram_reduce_grouped_launch(const GramReduceItem* items, int64_t n, int grid, hipStream_t s) {
+  if (n == 0) return NMF_OK;
+  hipLaunchKernelGGL(k_gram_reduce_grouped, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+  return launch_status("gram reduce (grouped)");
+}
+
+int gram_grouped_occupancy(int which, int* per_cu) {
+  hipError_t e = hipErrorInvalidValue;
+  if (which == kCapGram) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_gram_grouped, kThreads, 0);
+  return e == hipSuccess ? NMF_OK : NMF_EHIP;
 }
 
 }  // namespace nmf

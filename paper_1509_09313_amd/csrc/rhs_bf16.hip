@@ -7,6 +7,7 @@
 // HBM-bound where the FP32 MFMA form is compute-bound.
 #include <atomic>
 
+#include "batched.h"
 #include "nmf_common.h"
 
 namespace {
@@ -68,11 +69,12 @@ __device__ __forceinline__ v16f mfma_bf16(v8bf a, v8bf b, v16f c) {
 }
 
 // Y (K x k FP32, ld ldy) -> transposed BF16 planes Yth, Ytl (KP x ldt), rows
-// i >= k and columns >= K zero.  One block per 64 rows of Y.
-__global__ __launch_bounds__(256) void k_split_y(int64_t K, int k, int KP, const float* __restrict__ Y, int64_t ldy,
-                                                 uint16_t* __restrict__ Yth, uint16_t* __restrict__ Ytl, int64_t ldt) {
+// i >= k and columns >= K zero.  One block per 64 rows of Y (from row K0).
+__device__ __forceinline__ void split_y_chunk(int64_t K, int k, int KP, const float* __restrict__ Y, int64_t ldy,
+                                              uint16_t* __restrict__ Yth, uint16_t* __restrict__ Ytl, int64_t ldt,
+                                              int64_t K0) {
   __shared__ float tile[64][65];
-  const int64_t K0 = (int64_t)blockIdx.x * 64;
+  __syncthreads();
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int kk = e / 64, c = e - kk * 64;
     tile[kk][c] = (K0 + kk < K && c < k) ? Y[(K0 + kk) * ldy + c] : 0.0f;
@@ -90,43 +92,40 @@ __global__ __launch_bounds__(256) void k_split_y(int64_t K, int k, int KP, const
   }
 }
 
+__global__ __launch_bounds__(256) void k_split_y(int64_t K, int k, int KP, const float* __restrict__ Y, int64_t ldy,
+                                                 uint16_t* __restrict__ Yth, uint16_t* __restrict__ Ytl, int64_t ldt) {
+  split_y_chunk(K, k, KP, Y, ldy, Yth, Ytl, ldt, (int64_t)blockIdx.x * 64);
+}
+
+__global__ __launch_bounds__(256) void k_split_y_grouped(const nmf::SplitYItem* __restrict__ items, int64_t n) {
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::SplitYItem it = items[i];
+    split_y_chunk(it.K, it.k, it.KP, it.Y, it.ldy, it.Yth, it.Ytl, it.ldt, it.K0);
+  }
+}
+
 constexpr int kBTM = kTR;          // rows of B per block (4 waves x 32)
 constexpr int kBTK = kTC;          // contraction chunk (BF16 elements)
 constexpr int kBPitch = kBTK + 8;  // LDS pitch in uint16 (144 bytes: conflict-free 16-byte reads)
 
-// R (rows x k) = B (rows x K) * Y (K x k) with B in the padded BF16 form
-// (planes Rp x Cp) and Y as transposed BF16 planes (KP x ldt, ldt = Cp, zero
-// past K): D_t[i][j] = R[row0 + 32w + j][32t + i] from three MFMAs per
-// 16-wide K step (Yhi Bhi + Ylo Bhi + Yhi Blo).  The K index of a tile selects a range
-// of 64-column chunks (split-K); its partial goes to P + y * split_stride.
-// The grid is one-dimensional and XCD-aware: workgroups are dispatched to the
-// 8 XCDs round-robin, so launch index L runs on XCD L % 8; L is remapped to
-// the logical tile (L % 8) * (grid / 8) + L / 8, which gives every XCD a
-// contiguous range of logical tiles, row tile fastest.  All row tiles of one
-// K-range then run on the same XCD and share that range of Y in its L2.
-// SIDE (NMF_SIDE_W / NMF_SIDE_H) does not change the code; it only gives the
-// two products distinct kernel names in traces.
-template <int NT, int SIDE>
-__global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const uint16_t* __restrict__ B, int64_t Rp,
-                                                    int64_t nkc,
-                                                    const uint16_t* __restrict__ Yth, const uint16_t* __restrict__ Ytl,
-                                                    int64_t ldt, float* __restrict__ P, int64_t ldp, int64_t kc_per_split,
-                                                    int64_t split_stride, int64_t ntiles, int64_t nsplit) {
+// One 128-row tile of R = B * Y over the 64-column chunks [kc0, kc1) of the
+// contraction, written to out (ld ldp); B in the padded BF16 form (planes
+// Rp x Cp), Y as transposed BF16 planes (KP x ldt, ldt = Cp, zero past K).
+// Wave w holds D_t[i][j] = R[row0 + 32w + j][32t + i] and accumulates three
+// MFMAs per 16-wide K step (Yhi Bhi + Ylo Bhi + Yhi Blo).  Barrier-safe for
+// repeated calls from a persistent loop.
+template <int NT>
+__device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t* __restrict__ B, int64_t Rp,
+                                            int64_t nkc, const uint16_t* __restrict__ Yth,
+                                            const uint16_t* __restrict__ Ytl, int64_t ldt, float* __restrict__ out,
+                                            int64_t ldp, int64_t row0, int64_t kc0, int64_t kc1) {
   constexpr int KP = 32 * NT;
-  const int64_t per_xcd = gridDim.x / 8;
-  const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (lid >= ntiles * nsplit) return;
-  const int64_t bx = lid % ntiles, by = lid / ntiles;
   __shared__ __align__(16) uint16_t Bs[2][kBTM * kBPitch];
   __shared__ __align__(16) uint16_t Ys[2][KP * kBPitch];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j = lane & 31, h = lane >> 5;
-  const int64_t row0 = bx * kBTM;
-  const int64_t kc0 = by * kc_per_split;
-  const int64_t kc1 = (kc0 + kc_per_split < nkc) ? kc0 + kc_per_split : nkc;
   const int64_t Cp = nkc * kTC;
   const uint16_t* Bh = B + row0 * Cp;
-  const uint16_t* Bl = Bh + Rp * Cp;
 
   v16f acc[NT];
 #pragma unroll
@@ -193,7 +192,6 @@ __global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const u
     }
   }
 #undef NMF_LOAD_CHUNK
-  float* out = P + by * split_stride;
   const int64_t r = row0 + 32 * w + j;
   if (r < rows) {
 #pragma unroll
@@ -203,6 +201,43 @@ __global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const u
         const int c = 32 * tt + (v & 3) + 8 * (v >> 2) + 4 * h;
         if (c < k) out[r * ldp + c] = acc[tt][v];
       }
+  }
+  __syncthreads();
+}
+
+// R (rows x k) = B (rows x K) * Y (K x k) with B in the padded BF16 form
+// (planes Rp x Cp) and Y as transposed BF16 planes (KP x ldt, ldt = Cp, zero
+// past K).  The grid is one-dimensional and XCD-aware: workgroups are
+// dispatched to the 8 XCDs round-robin, so launch index L runs on XCD L % 8;
+// L is remapped to the logical tile (L % 8) * (grid / 8) + L / 8, which gives
+// every XCD a contiguous range of logical tiles, row tile fastest.  All row
+// tiles of one K-range then run on the same XCD and share that range of Y in
+// its L2.  The K index of a logical tile selects a range of 64-column chunks
+// (split-K); its partial goes to P + split * split_stride.  SIDE
+// (NMF_SIDE_W / NMF_SIDE_H) does not change the code; it only gives the two
+// products distinct kernel names in traces.
+template <int NT, int SIDE>
+__global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const uint16_t* __restrict__ B, int64_t Rp,
+                                                    int64_t nkc,
+                                                    const uint16_t* __restrict__ Yth, const uint16_t* __restrict__ Ytl,
+                                                    int64_t ldt, float* __restrict__ P, int64_t ldp, int64_t kc_per_split,
+                                                    int64_t split_stride, int64_t ntiles, int64_t nsplit) {
+  const int64_t per_xcd = gridDim.x / 8;
+  const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (lid >= ntiles * nsplit) return;
+  const int64_t bx = lid % ntiles, by = lid / ntiles;
+  const int64_t kc0 = by * kc_per_split;
+  const int64_t kc1 = (kc0 + kc_per_split < nkc) ? kc0 + kc_per_split : nkc;
+  bf16x3_tile<NT>(rows, k, B, Rp, nkc, Yth, Ytl, ldt, P + by * split_stride, ldp, bx * kBTM, kc0, kc1);
+}
+
+// Grouped form: a persistent walk over tiles of many products.
+template <int NT>
+__global__ __launch_bounds__(256) void k_rhs_bf16x3_grouped(const nmf::Bf16Item* __restrict__ items, int64_t n) {
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::Bf16Item it = items[i];
+    bf16x3_tile<NT>(it.rows, it.k, it.B, it.Rp, it.nkc, it.Yth, it.Ytl, it.ldt, it.out, it.ldp, it.row0, it.kc0,
+                    it.kc1);
   }
 }
 
@@ -215,6 +250,21 @@ __global__ void k_reduce_splits(int64_t rows, int k, int S, const float* __restr
   double s = 0.0;
   for (int sp = 0; sp < S; ++sp) s += (double)P[sp * split_stride + e];
   R[row * ldr + c] = (float)s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_splits_grouped(const nmf::SplitReduceItem* __restrict__ items,
+                                                               int64_t n) {
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::SplitReduceItem it = items[i];
+    const int64_t e = it.e0 + threadIdx.x;
+    if (e < it.rows * it.k) {
+      const int64_t row = e / it.k;
+      const int c = (int)(e - row * it.k);
+      double s = 0.0;
+      for (int sp = 0; sp < it.S; ++sp) s += (double)it.P[sp * it.stride + e];
+      it.R[row * it.ldr + c] = (float)s;
+    }
+  }
 }
 
 struct Bf16Plan {
@@ -329,6 +379,39 @@ int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const f
     NMF_TRY(launch_status("rhs bf16x3: reduce"));
   }
   return NMF_OK;
+}
+
+int split_y_grouped_launch(const SplitYItem* items, int64_t n, int grid, hipStream_t s) {
+  if (n == 0) return NMF_OK;
+  hipLaunchKernelGGL(k_split_y_grouped, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+  return launch_status("split Y (grouped)");
+}
+
+int bf16x3_grouped_launch(int NT, const Bf16Item* items, int64_t n, int grid, hipStream_t s) {
+  if (n == 0) return NMF_OK;
+  if (NT == 1)
+    hipLaunchKernelGGL(k_rhs_bf16x3_grouped<1>, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+  else
+    hipLaunchKernelGGL(k_rhs_bf16x3_grouped<2>, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+  return launch_status("rhs bf16x3 (grouped)");
+}
+
+int split_reduce_grouped_launch(const SplitReduceItem* items, int64_t n, int grid, hipStream_t s) {
+  if (n == 0) return NMF_OK;
+  hipLaunchKernelGGL(k_reduce_splits_grouped, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+  return launch_status("split reduce (grouped)");
+}
+
+int bf16_grouped_occupancy(int which, int* per_cu) {
+  hipError_t e = hipErrorInvalidValue;
+  if (which == kCapSplitY) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_split_y_grouped, 256, 0);
+  if (which == kCapBf16NT1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_rhs_bf16x3_grouped<1>, 256, 0);
+  if (which == kCapBf16NT2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_rhs_bf16x3_grouped<2>, 256, 0);
+  if (which == kCapReduce)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_reduce_splits_grouped, 256, 0);
+  return e == hipSuccess ? NMF_OK : NMF_EHIP;
 }
 
 }  // namespace nmf

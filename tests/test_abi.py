@@ -86,3 +86,41 @@ def test_struct_layouts_match_header(L):
     # the Python mirror must agree field for field.
     assert ctypes.sizeof(L.nmf_iter_stats) == 8 * (2 + 2 * L.NMF_BPP_COUNTERS + 2)
     assert L.nmf_matrix.fro2.offset == ctypes.sizeof(L.nmf_matrix) - 8
+    assert ctypes.sizeof(L.nmf_batch_problem) == 8 * 2 + 4 * 2 + 8 * 6
+    assert ctypes.sizeof(L.nmf_batch_tune) == 4 * 6
+
+
+def test_batch_host_validation_without_gpu(L):
+    lib = L.lib()
+    G = 16  # a non-null stand-in; nothing here dereferences device pointers
+    P = (L.nmf_batch_problem * 2)()
+    P[0] = L.nmf_batch_problem(300, 200, 10, 0, G, G, G, 10, G, 10)
+    P[1] = L.nmf_batch_problem(1000, 513, 50, 0, G, G, G, 50, G, 50)
+    nb = ctypes.c_size_t(0)
+    assert lib.nmf_batch_workspace_bytes(2, P, None, ctypes.byref(nb)) == L.NMF_OK
+    t = L.batch_tune_default()
+    nd = ctypes.c_size_t(0)
+    assert lib.nmf_batch_workspace_bytes(2, P, ctypes.byref(t), ctypes.byref(nd)) == L.NMF_OK
+    # the size for any tuning the autotuner tries covers the default one
+    assert 0 < nd.value <= nb.value
+    # the factors alone: W, Ht, their backups, Gram matrices, right-hand sides
+    assert nd.value > 4 * (2 * (300 + 200) * 10 + 2 * (1000 + 513) * 50)
+    assert lib.nmf_batch_workspace_bytes(0, P, None, ctypes.byref(nb)) == L.NMF_EINVAL
+    bad = (L.nmf_batch_problem * 1)()
+    bad[0] = L.nmf_batch_problem(300, 200, 0, 0, G, G, G, 10, G, 10)
+    assert lib.nmf_batch_workspace_bytes(1, bad, None, ctypes.byref(nb)) == L.NMF_EINVAL
+    bad[0] = L.nmf_batch_problem(300, 200, 10, 0, G, G, G, 4, G, 10)
+    assert lib.nmf_batch_workspace_bytes(1, bad, None, ctypes.byref(nb)) == L.NMF_EINVAL
+    bad[0] = L.nmf_batch_problem(300, 200, 10, 0, None, G, G, 10, G, 10)
+    assert lib.nmf_batch_workspace_bytes(1, bad, None, ctypes.byref(nb)) == L.NMF_EINVAL
+    t.warm_prev = 2
+    assert lib.nmf_batch_workspace_bytes(2, P, ctypes.byref(t), ctypes.byref(nb)) == L.NMF_EINVAL
+    t.warm_prev = 1
+    t.bpp_problems = 10
+    assert lib.nmf_batch_workspace_bytes(2, P, ctypes.byref(t), ctypes.byref(nb)) == L.NMF_EINVAL
+    # a workspace one byte short is refused before anything reaches the device
+    h = ctypes.c_void_p()
+    assert lib.nmf_batch_plan_create(2, P, None, ctypes.c_void_p(G), nd.value - 1, ctypes.byref(h)) == L.NMF_EWORKSPACE
+    assert h.value is None
+    assert lib.nmf_batch_iterate(None, 1, None, 0, None) == L.NMF_EINVAL
+    assert lib.nmf_batch_graph_create(None, 1, None, 0, None, ctypes.byref(h)) == L.NMF_EINVAL
