@@ -185,35 +185,56 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
       const double rf0 = useInv ? z : f;
       bool retry = false;
       double x, y;
-      if (__ballot(__popcll(Pv) > kSmall) == 0) {
+      const int sp = __popcll(Pv);
+      if (__ballot(sp != 0) == 0) {
+        // No pivots anywhere in the wavefront: the solve is a read-out
+        // (inverse form: x_F = z, y = 0; direct form: x = 0, y = -f).
+        const bool inF = (Fe >> p) & 1ull;
+        if (useInv) {
+          x = inF ? z : 0.0;
+          y = 0.0;
+        } else {
+          x = 0.0;
+          y = inF ? 0.0 : -f;
+        }
+      } else if (__ballot(sp > kSmall) == 0) {
         // Small pivot sets (every problem of the wavefront): each lane reads
         // the entries it needs, M[p][j] for the pivots j, and solves the
         // s x s system M_PP u = rhs_P redundantly by LDL^T in index order
         // (the same pivots and pivot tests as the elimination below).
+        // The largest pivot set of the wavefront bounds the (uniform) steps.
+        int smax = 0;
+#pragma unroll
+        for (int t = 1; t <= kSmall; ++t)
+          if (__ballot(sp >= t) != 0) smax = t;
         int jj[kSmall];
         bool vt[kSmall];
         uint64_t rem = Pv;
 #pragma unroll
         for (int t = 0; t < kSmall; ++t) {
-          vt[t] = rem != 0ull;
-          jj[t] = rem != 0ull ? (__ffsll((unsigned long long)rem) - 1) : 0;
-          rem &= rem - 1ull;
+          vt[t] = false;
+          jj[t] = 0;
+          if (t < smax) {
+            vt[t] = rem != 0ull;
+            jj[t] = rem != 0ull ? (__ffsll((unsigned long long)rem) - 1) : 0;
+            rem &= rem - 1ull;
+          }
         }
         rfv[wave][lane] = rf0;
         wave_lds_sync();
         double bt[kSmall], mc[kSmall], dg[kSmall];
 #pragma unroll
         for (int t = 0; t < kSmall; ++t) {
-          bt[t] = vt[t] ? rfv[wave][base + jj[t]] : 0.0;
-          mc[t] = vt[t] ? Mrow[jj[t] * K + p] : 0.0;
-          dg[t] = vt[t] ? Mrow[jj[t] * K + jj[t]] : 1.0;
+          bt[t] = 0.0;
+          mc[t] = 0.0;
+          dg[t] = 1.0;
+          if (t < smax) {
+            bt[t] = vt[t] ? rfv[wave][base + jj[t]] : 0.0;
+            mc[t] = vt[t] ? Mrow[jj[t] * K + p] : 0.0;
+            dg[t] = vt[t] ? Mrow[jj[t] * K + jj[t]] : 1.0;
+          }
         }
         wave_lds_sync();
-        // the largest pivot set of the wavefront bounds the (uniform) steps
-        int smax = 0;
-#pragma unroll
-        for (int t = 0; t < kSmall; ++t)
-          if (__ballot(vt[t]) != 0) smax = t + 1;
         double Lm[kSmall][kSmall], rinv[kSmall], dd[kSmall], u[kSmall];
 #pragma unroll
         for (int a = 0; a < kSmall; ++a) {
