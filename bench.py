@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched measurement")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--pmc", action="store_true", help="copy calibration + dominant kernels only (for rocprofv3 --pmc)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 class Bench:

@@ -96,6 +96,12 @@ int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* 
  *   call; R = hi*hi + hi*lo + lo*hi (lo*lo dropped), FP32 accumulation.  A
  *   itself is not read in this mode and may be NULL.
  * R: FP32, leading dimension ldr >= k (device). */
+/* Error analysis: the longest FP32 accumulation (number of products added
+ * into one FP32 accumulator) that nmf_rhs_dense uses for these arguments on
+ * the current device (split-K partials are summed in FP64 afterwards), so
+ * |R - R_exact(operands)| <= terms * 2^-24 * (|A| |Y|) entrywise, the
+ * operands being FP32 A and Y, or for NMF_BF16X3 the three BF16 products. */
+int nmf_rhs_dense_chain(int side, int64_t m, int64_t n, int k, int prec, int64_t* terms);
 int nmf_rhs_dense_workspace_bytes(int side, int64_t m, int64_t n, int k, int prec, size_t* bytes);
 int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* B_bf16,
                   const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* ws, size_t ws_bytes,

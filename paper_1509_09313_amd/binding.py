@@ -99,6 +99,7 @@ def lib():
             "nmf_gram_workspace_bytes": ([i64, ci, sz], ci),
             "nmf_gram": ([i64, ci, vp, i64, vp, vp, ctypes.c_size_t, vp], ci),
             "nmf_rhs_dense_workspace_bytes": ([ci, i64, i64, ci, ci, sz], ci),
+            "nmf_rhs_dense_chain": ([ci, i64, i64, ci, ci, ctypes.POINTER(i64)], ci),
             "nmf_rhs_dense": ([ci, i64, i64, ci, vp, i64, vp, vp, i64, vp, i64, ci, vp, ctypes.c_size_t, vp], ci),
             "nmf_split_bf16_bytes": ([i64, i64, ci], ctypes.c_size_t),
             "nmf_split_bf16": ([i64, i64, vp, i64, ci, vp, vp], ci),
@@ -185,6 +186,13 @@ def nmf_gram(X, G=None):
     ws = _ws(nb.value)
     _check(lib().nmf_gram(rows, k, _ptr(X), _ld(X), _ptr(G), _ptr(ws), nb.value, _stream()))
     return G
+
+
+def rhs_dense_chain(side, m, n, k, prec=NMF_F32) -> int:
+    """Longest FP32 accumulation chain of nmf_rhs_dense on the current device."""
+    t = i64(0)
+    _check(lib().nmf_rhs_dense_chain(side, m, n, k, prec, ctypes.byref(t)))
+    return int(t.value)
 
 
 def nmf_split_bf16(X, transpose=False):

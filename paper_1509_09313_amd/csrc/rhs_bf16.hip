@@ -345,6 +345,14 @@ int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch
   return NMF_OK;
 }
 
+// Longest FP32 accumulation (products per accumulator) of a launch on the
+// current device: three products per contraction index over one split.
+int64_t bf16x3_chain(int side, int64_t m, int64_t n, int k) {
+  const int KP = k <= 32 ? 32 : 64;
+  const Bf16Plan p = bf16_plan(side, m, n, k, bf16_capacity(KP));
+  return 3 * p.kcps * kTC;
+}
+
 int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const float* Y, int64_t ldy, float* R,
                   int64_t ldr, void* scratch, hipStream_t s) {
   const int KP = k <= 32 ? 32 : 64;

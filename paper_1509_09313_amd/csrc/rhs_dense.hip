@@ -269,6 +269,7 @@ namespace nmf {
 int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch);
 int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const float* Y, int64_t ldy, float* R,
                   int64_t ldr, void* scratch, hipStream_t s);
+int64_t bf16x3_chain(int side, int64_t m, int64_t n, int k);
 }
 
 namespace nmf {
@@ -313,6 +314,22 @@ static int check_rhs_args(int side, int64_t m, int64_t n, int k, int prec, const
     if (m > 0 && n > 0 && !A) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: A is null");
   } else {
     if (m > 0 && n > 0 && !Bt) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense: the tiled BF16 operand is null");
+  }
+  return NMF_OK;
+}
+
+extern "C" int nmf_rhs_dense_chain(int side, int64_t m, int64_t n, int k, int prec, int64_t* terms) {
+  if (!terms) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_chain: terms is null");
+  if (side != NMF_SIDE_W && side != NMF_SIDE_H) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_chain: bad side");
+  if (prec != NMF_F32 && prec != NMF_BF16X3) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_chain: bad prec");
+  if (!nmf::valid_k(k) || m < 0 || n < 0) return nmf::fail(NMF_EINVAL, "nmf_rhs_dense_chain: bad sizes");
+  if (prec == NMF_BF16X3) {
+    *terms = nmf::bf16x3_chain(side, m, n, k);
+  } else if (side == NMF_SIDE_W) {
+    *terms = n;
+  } else {
+    const HSplit sp = h_split(m, n);
+    *terms = sp.S > 1 ? sp.rows_per_split : m;
   }
   return NMF_OK;
 }
