@@ -90,23 +90,40 @@ __global__ __launch_bounds__(64) void k_obj_dense(int64_t m, int64_t n, int k, c
   }
   double sr = 0.0, sa = 0.0;
   const int64_t ntiles = (n + 31) / 32;
-  for (int64_t tl = tile0; tl < ntiles && tl < tile0 + kObjColTiles; ++tl) {
-    const int64_t c0 = tl * 32;
-    const int64_t jc = c0 + i;
+  const int64_t tend = (tile0 + kObjColTiles < ntiles) ? tile0 + kObjColTiles : ntiles;
+  // the next tile's H^T operands and A entries are loaded while the current
+  // tile is reduced (acc[v] = (W Ht^T)[r0 + ii][c0 + i], ii = (v&3) + 8(v>>2) + 4h)
+  float hn[NS], an[16];
+#define NMF_OBJ_LOAD(TL)                                                              \
+  do {                                                                                \
+    const int64_t jn_ = (TL) * 32 + i;                                                \
+    _Pragma("unroll") for (int s_ = 0; s_ < NS; ++s_) {                               \
+      const int c_ = 2 * s_ + h;                                                      \
+      hn[s_] = (jn_ < n && c_ < k) ? Ht[jn_ * k + c_] : 0.0f;                         \
+    }                                                                                 \
+    _Pragma("unroll") for (int v_ = 0; v_ < 16; ++v_) {                               \
+      const int64_t row_ = r0 + (v_ & 3) + 8 * (v_ >> 2) + 4 * h;                     \
+      an[v_] = (jn_ < n && row_ < m) ? A[row_ * lda + jn_] : 0.0f;                    \
+    }                                                                                 \
+  } while (0)
+  if (tile0 < tend) NMF_OBJ_LOAD(tile0);
+  for (int64_t tl = tile0; tl < tend; ++tl) {
+    float hb[NS], av[16];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) hb[s] = hn[s];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) av[v] = an[v];
+    if (tl + 1 < tend) NMF_OBJ_LOAD(tl + 1);
+    const int64_t jc = tl * 32 + i;
     v16f acc = v16f{};
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int c = 2 * s + h;
-      const float hb = (jc < n && c < k) ? Ht[jc * k + c] : 0.0f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[s], hb, acc, 0, 0, 0);
-    }
-    // acc[v] = (W Ht^T)[r0 + ii][c0 + i] with ii = (v&3) + 8(v>>2) + 4h
+    for (int s = 0; s < NS; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[s], hb[s], acc, 0, 0, 0);
     if (jc < n) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t row = r0 + (v & 3) + 8 * (v >> 2) + 4 * h;
         if (row < m) {
-          const double a = A[row * lda + jc];
+          const double a = av[v];
           const double e = a - (double)acc[v];
           sr += e * e;
           sa += a * a;
@@ -114,6 +131,7 @@ __global__ __launch_bounds__(64) void k_obj_dense(int64_t m, int64_t n, int k, c
       }
     }
   }
+#undef NMF_OBJ_LOAD
   sr = wave_sum_f64(sr);
   sa = wave_sum_f64(sa);
   if (lane == 0) {
