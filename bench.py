@@ -60,7 +60,9 @@ def parse(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched measurement")
     ap.add_argument("--batched-reps", type=int, default=3)
-    ap.add_argument("--pmc", action="store_true", help="copy calibration + dominant kernels only (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc", action="store_true", help="copy calibration + product kernels only (for rocprofv3 --pmc)")
+    ap.add_argument("--sparse", action="store_true",
+                    help="the CSR workload (207360 x 138240): alone, or with --pmc its SpMM kernels too")
     return ap.parse_args(argv)
 
 
@@ -71,7 +73,7 @@ class Bench:
         from nmf_inputs import configs as C
         from nmf_inputs import device as gen
         from paper_1509_09313_amd import binding as L
-        self.torch, self.C, self.L, self.a = torch, C, L, a
+        self.torch, self.C, self.L, self.a, self.gen = torch, C, L, a, gen
         self.seed = C.seed_for(5)
         m, n, k = a.m, a.n, a.k
         t0 = time.perf_counter()
@@ -338,9 +340,22 @@ def batched(a):
             "algorithmic_bytes_per_iteration": alg, "achieved_GBps": ach, "hbm_frac": ach / HBM_PEAK_GBS}
 
 
+def sparse_inputs(torch):
+    """The CSR workload (207,360 x 138,240, density 1e-3) built on the host
+    from its seeded recipe and uploaded: CSR(A) and CSR(A^T)."""
+    from nmf_inputs import configs as C
+    seed, m, n = C.seed_for(3), 207_360, 138_240
+    rp, ci, va = C.sparse_csr(seed, m, n, 1e-3)
+    rpt, cit, vat = C.csr_transpose(m, n, rp, ci, va)
+    d = [torch.from_numpy(x).cuda() for x in (rp, ci, va, rpt, cit, vat)]
+    return seed, m, n, d
+
+
 def pmc_mode(a):
-    """Launches a plain copy of known size, then the dominant kernels a few
-    times each, for rocprofv3 counter collection (FETCH_SIZE / WRITE_SIZE)."""
+    """Launches a plain copy of known size, then each product kernel a few
+    times (BF16x3 and FP32 on the video-like matrix, both Gram passes, and
+    with --sparse the CSR products of the sparse workload), for rocprofv3
+    counter collection (FETCH_SIZE / WRITE_SIZE, MFMA busy cycles)."""
     import torch
     b = Bench(a)
     L = b.L
@@ -352,8 +367,70 @@ def pmc_mode(a):
     for _ in range(3):
         L.nmf_rhs_dense(L.NMF_SIDE_W, None, b.Ht0, prec=L.NMF_BF16X3, B_bf16=bt, m=a.m, n=a.n)
         L.nmf_rhs_dense(L.NMF_SIDE_H, None, b.W0, prec=L.NMF_BF16X3, B_bf16=btt, m=a.m, n=a.n)
+    for _ in range(3):
+        L.nmf_rhs_dense(L.NMF_SIDE_W, b.A, b.Ht0)
+        L.nmf_rhs_dense(L.NMF_SIDE_H, b.A, b.W0)
+    for _ in range(3):
+        L.nmf_gram(b.W0)
+        L.nmf_gram(b.Ht0)
+    if a.sparse:
+        seed, m, n, d = sparse_inputs(torch)
+        W0, Ht0 = b.gen.init_factors(seed, m, n, 50)
+        for _ in range(3):
+            L.nmf_rhs_csr(d[0], d[1], d[2], Ht0, m, n)
+            L.nmf_rhs_csr(d[3], d[4], d[5], W0, n, m)
     torch.cuda.synchronize()
     print(json.dumps({"pmc": "done", "copy_bytes": 2 * src.numel() * 4}))
+
+
+def sparse_mode(a):
+    """The CSR workload at full size: plain FP32 SpMM right-hand sides, FP64
+    Gram and BPP, `iters` iterations per step from the seeded start (cold
+    BPP), with the SpMM rate on algorithmic bytes."""
+    import numpy as np
+    import torch
+
+    from nmf_inputs import device as gen
+    from paper_1509_09313_amd import binding as L
+    t0 = time.perf_counter()
+    seed, m, n, d = sparse_inputs(torch)
+    k, T = 50, 30
+    W0, Ht0 = gen.init_factors(seed, m, n, k)
+    M = L.Matrix(csr=(d[0], d[1], d[2]), csr_t=(d[3], d[4], d[5]), shape=(m, n))
+    torch.cuda.synchronize()
+    print(f"# sparse inputs: {time.perf_counter() - t0:.1f}s (host generation)", file=sys.stderr, flush=True)
+    W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
+    run = L.Anls(M, k, L.make_opts(prec=L.NMF_F32, trace=True))
+    stats = L.new_stats(T)
+
+    def step(timer=None):
+        W.copy_(W0)
+        Ht.copy_(Ht0)
+        if timer:
+            timer.attach(run.opts)
+        run.run(W, Ht, T, stats)
+        if timer:
+            timer.detach(run.opts)
+
+    t = timed(step, a.steps, a.warmup)
+    tm = L.PhaseTimer(T)
+    step(tm)
+    torch.cuda.synchronize()
+    ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
+    tm.close()
+    r = float(L.nmf_objective(M, W, Ht)[0])
+    nnz = int(d[2].numel())
+    alg_w = 12.0 * nnz + 8.0 * (m + 1) + 4.0 * n * k + 4.0 * m * k
+    alg_h = 12.0 * nnz + 8.0 * (n + 1) + 4.0 * m * k + 4.0 * n * k
+    st = L.decode_stats(stats)
+    res = {"workload": f"CSR {m}x{n}, density 1e-3 ({nnz} nonzeros), k={k}, {T} iterations per step, "
+                       f"FP32 SpMM, FP64 Gram/BPP, cold BPP",
+           "iters_per_s": T * a.steps / t, "ms_per_step": t / a.steps * 1e3, "final_r": r,
+           "phase_ms_per_iter": ph,
+           "spmm_w_GBps": alg_w / (ph["rhs_w"] * 1e-3) / 1e9, "spmm_h_GBps": alg_h / (ph["rhs_h"] * 1e-3) / 1e9,
+           "bpp_rounds_per_problem": float(np.mean([(s["bpp_w"][0] + s["bpp_h"][0]) / (m + n) for s in st])),
+           "capped": int(sum(s["capped"] for s in st))}
+    print(json.dumps({"sparse": res}))
 
 
 def main():
@@ -364,6 +441,9 @@ def main():
         sys.exit(2)
     if a.pmc:
         pmc_mode(a)
+        return
+    if a.sparse:
+        sparse_mode(a)
         return
     import numpy as np
     b = Bench(a)
