@@ -122,16 +122,24 @@ __global__ __launch_bounds__(256) void k_rhs_w_f32(int64_t m, int64_t n, int k, 
 constexpr int kHCols = 128;  // columns of A per wave
 constexpr int kHUnroll = 8;  // row pairs in flight per lane
 
+// The grid is one-dimensional and XCD-aware (launch index L runs on XCD
+// L % 8; L -> logical (L % 8) * (grid / 8) + L / 8, column group fastest), so
+// all column groups of one row range run on one XCD and share that range of
+// Y in its L2.
 template <int NT, bool VEC>
 __global__ __launch_bounds__(64) void k_rhs_h_f32(int64_t m, int64_t n, int k, const float* __restrict__ A,
                                                   int64_t lda, const float* __restrict__ Y, int64_t ldy,
                                                   float* __restrict__ P, int64_t ldp, int64_t rows_per_split,
-                                                  int64_t split_stride) {
+                                                  int64_t split_stride, int64_t ngroups, int64_t nsplit) {
+  const int64_t per_xcd = gridDim.x / 8;
+  const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (lid >= ngroups * nsplit) return;
+  const int64_t gx = lid % ngroups, gy = lid / ngroups;
   const int lane = threadIdx.x;
   const int j = lane & 31, h = lane >> 5;
-  const int64_t c0 = (int64_t)blockIdx.x * kHCols;
+  const int64_t c0 = gx * kHCols;
   const int64_t col = c0 + 4 * j;
-  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r_begin = gy * rows_per_split;
   const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
 
   v16f acc[4][NT];
@@ -172,7 +180,7 @@ __global__ __launch_bounds__(64) void k_rhs_h_f32(int64_t m, int64_t n, int k, c
     }
   }
   // D_{q,tt}[i][j] = R[c0 + 4j + q][32 tt + i]
-  float* out = P + (int64_t)blockIdx.y * split_stride;
+  float* out = P + gy * split_stride;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t row = col + q;
@@ -244,14 +252,14 @@ int launch_h_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const
   float* P = sp.S > 1 ? partial : R;
   const int64_t ldp = sp.S > 1 ? k : ldr;
   const int64_t stride = sp.S > 1 ? n * k : 0;
-  const dim3 grid((unsigned)sp.colgroups, (unsigned)sp.S);
+  const dim3 grid((unsigned)(nmf::cdiv(sp.colgroups * sp.S, 8) * 8));
   nmf::mark_begin(s);
   if (vec)
     hipLaunchKernelGGL((k_rhs_h_f32<NT, true>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
-                       sp.rows_per_split, stride);
+                       sp.rows_per_split, stride, sp.colgroups, (int64_t)sp.S);
   else
     hipLaunchKernelGGL((k_rhs_h_f32<NT, false>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
-                       sp.rows_per_split, stride);
+                       sp.rows_per_split, stride, sp.colgroups, (int64_t)sp.S);
   nmf::mark_end(s);
   NMF_TRY(nmf::launch_status("rhs side H (fp32)"));
   if (sp.S > 1) {
