@@ -121,7 +121,10 @@ int nmf_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, int 
  * R (rows x k) = A_csr (rows x cols) * Y (cols x k, ldy >= k).  Pass CSR(A)
  * with Y = Ht for A H^T, CSR(A^T) with Y = W for (W^T A)^T.  rowptr int64
  * (rows + 1), colidx int32 in [0, cols), vals FP32.  One wavefront per row,
- * products accumulated in FP64 in storage order, stored as FP32. */
+ * products accumulated in FP64 in storage order, stored as FP32.  The cost is
+ * gathering one row of Y per nonzero: an ldy whose rows never straddle a
+ * 128-byte line (a power of two >= k for k <= 32, else a multiple of 32) is
+ * markedly faster; nmf_anls_iter copies its factor to such a layout itself. */
 int nmf_rhs_csr(int64_t rows, int64_t cols, int k, const int64_t* rowptr, const int32_t* colidx,
                 const float* vals, const float* Y, int64_t ldy, float* R, int64_t ldr, void* stream);
 

@@ -99,6 +99,9 @@ int plan_anls(const nmf_matrix* A, int k, const nmf_opts* o, nmf::Carver& c, Pla
   if (A->kind == NMF_DENSE) {
     NMF_TRY(nmf::rhs_dense_plan(NMF_SIDE_W, m, n, k, o->prec, c, &P->rhs_w));
     NMF_TRY(nmf::rhs_dense_plan(NMF_SIDE_H, m, n, k, o->prec, c, &P->rhs_h));
+  } else if (nmf::csr_pad_ld(k) != k) {
+    // line-aligned copy of the SpMM's factor (Ht, then W: one after the other)
+    P->rhs_w = P->rhs_h = c.take<float>((size_t)mx * nmf::csr_pad_ld(k));
   }
   P->cross = c.take<double>(1);
   P->gdot = c.take<double>(1);
@@ -147,9 +150,10 @@ int check_matrix(const nmf_matrix* A) {
 
 int rhs(const nmf_matrix* A, int side, int k, int prec, const float* Y, float* R, void* scratch, hipStream_t s) {
   if (A->kind == NMF_CSR) {
+    float* ypad = static_cast<float*>(scratch);
     if (side == NMF_SIDE_W)
-      return nmf::rhs_csr_launch(A->m, A->n, k, A->rowptr, A->colidx, A->vals, Y, k, R, k, s);
-    return nmf::rhs_csr_launch(A->n, A->m, k, A->rowptr_t, A->colidx_t, A->vals_t, Y, k, R, k, s);
+      return nmf::rhs_csr_launch(A->m, A->n, k, A->rowptr, A->colidx, A->vals, Y, k, R, k, ypad, s);
+    return nmf::rhs_csr_launch(A->n, A->m, k, A->rowptr_t, A->colidx_t, A->vals_t, Y, k, R, k, ypad, s);
   }
   const void* bt = side == NMF_SIDE_W ? A->A_bf16 : A->At_bf16;
   return nmf::rhs_dense_launch(side, A->m, A->n, k, A->A, A->lda, bt, Y, k, R, k, prec, scratch, s);

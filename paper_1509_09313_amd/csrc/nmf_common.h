@@ -59,8 +59,12 @@ int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, v
 int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* Bt,
                      const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s);
 
+// CSR products.  csr_pad_ld: a leading dimension for Y whose rows never
+// straddle a 128-byte line; with ypad (cols x csr_pad_ld(k) floats) Y is
+// first copied there.
+int64_t csr_pad_ld(int k);
 int rhs_csr_launch(int64_t rows, int64_t cols, int k, const int64_t* rowptr, const int32_t* colidx,
-                   const float* vals, const float* Y, int64_t ldy, float* R, int64_t ldr,
+                   const float* vals, const float* Y, int64_t ldy, float* R, int64_t ldr, float* ypad,
                    hipStream_t s);
 
 int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X,

@@ -286,3 +286,29 @@ def test_sparse_full_sampled():
     # G_H, which moves solutions by far less than 4 ulp32
     assert not bad.any()
     assert st[0]["capped"] == 0
+
+
+def test_csr_gather_beyond_4gib():
+    """A factor Y above 4 GiB (16.8 M rows x 64 floats) takes the global-load
+    gather path (buffer offsets are 32-bit): bit-identical to the oracle on
+    rows whose entries reach the top of Y."""
+    rows, cols, k, per_row = 2000, 16_800_000, 64, 40
+    rng = np.random.default_rng(4)
+    lists = [np.unique(rng.integers(0, cols, per_row)) for _ in range(rows)]
+    lists[0] = np.array([0, cols - 1])
+    lists[1] = np.arange(cols - 300, cols)
+    lists[2] = np.array([], dtype=np.int64)
+    rp = np.concatenate([[0], np.cumsum([len(x) for x in lists])]).astype(np.int64)
+    ci = np.concatenate(lists).astype(np.int32)
+    va = rng.uniform(0.0, 1.0, len(ci)).astype(np.float32)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    Y = torch.rand((cols, k), generator=g, device="cuda")
+    assert Y.numel() * 4 > 2 ** 32
+    R = L.nmf_rhs_csr(cuda(rp), cuda(ci), cuda(va), Y, rows, cols).cpu().numpy()
+    used, inv = np.unique(ci, return_inverse=True)
+    Ysub = Y[cuda(used.astype(np.int64))].cpu().numpy().astype(np.float64)
+    del Y
+    torch.cuda.empty_cache()
+    ref = oracle.rhs_csr(rp, inv.astype(np.int32), va, Ysub).astype(np.float32)
+    assert np.array_equal(R, ref)

@@ -90,6 +90,24 @@ def test_rhs_csr_bit_exact(m, n, k, density):
     assert np.array_equal(Rh, oracle.rhs_csr(rpt, cit, vat, W.astype(np.float64)).astype(np.float32))
 
 
+@pytest.mark.parametrize("m,n,k,ld", [(2000, 1500, 50, 64), (3000, 2500, 30, 32), (700, 900, 5, 8),
+                                      (300, 200, 64, 70), (130, 257, 33, 64)])
+def test_rhs_csr_padded_and_strided(m, n, k, ld):
+    """Y and R with leading dimensions above k (the line-aligned layout the
+    ANLS driver uses, and an odd one) give the oracle's bits; R's padding
+    columns are left alone.  Rows hold 0 to ~300 entries (several 128-entry
+    blocks and 32-entry chunks, ragged ends)."""
+    rp, ci, va = C.sparse_csr(23 + m, m, n, 0.3 if m <= 300 else 0.02)
+    rng = np.random.default_rng(k)
+    Ht = rng.uniform(0.0, 1.0, (n, k)).astype(np.float32)
+    Yb = torch.full((n, ld), float("nan"), dtype=torch.float32, device="cuda")
+    Yb[:, :k] = cuda(Ht)
+    Rb = torch.full((m, k + 3), -1.0, dtype=torch.float32, device="cuda")
+    L.nmf_rhs_csr(cuda(rp), cuda(ci), cuda(va), Yb[:, :k], m, n, R=Rb[:, :k])
+    assert np.array_equal(Rb[:, :k].cpu().numpy(), oracle.rhs_csr(rp, ci, va, Ht.astype(np.float64)).astype(np.float32))
+    assert torch.all(Rb[:, k:] == -1.0)
+
+
 # ------------------------------------------------------------------ BPP ----
 def nmf_like_problems(rng, k, batch, rows=None):
     """G = C^T C with nonnegative C (an NMF Gram) and right-hand sides
