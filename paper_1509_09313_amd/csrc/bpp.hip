@@ -138,28 +138,27 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
   unsigned long long c_rounds = 0, c_solves = 0, c_f1 = 0, c_f2 = 0, c_f3 = 0, c_steps = 0;
 
   // the next problem's right-hand side and start set are loaded while the
-  // current one is solved.  The loads take clamped (always valid) indices
-  // and no branch, and their raw values are masked only when used, one
-  // iteration later: a masked or branched load would make the compiler wait
-  // for it at once.
+  // current one is solved
   const int64_t gstride = g_step;
   int64_t g = g_first;
-  const int pc = p < k ? p : k - 1;
-  float f_raw = 0.0f;
-  uint64_t m_raw = 0;
-  auto prefetch = [&](int64_t bn) {
-    const int64_t bc = bn < b1 ? bn : b1 - 1;
-    f_raw = R[bc * ldr + pc];
-    if (mask_in) m_raw = mask_in[bc];
-  };
-  if (b0 + g * P < b1) prefetch(b0 + g * P + sub);
+  float f_next = 0.0f;
+  uint64_t m_next = 0;
+  {
+    const int64_t b = b0 + g * P + sub;
+    if (lane_in && b < b1 && p < k) f_next = R[b * ldr + p];
+    if (lane_in && b < b1 && mask_in) m_next = mask_in[b];
+  }
   for (; b0 + g * P < b1; g += gstride) {
     const int64_t b = b0 + g * P + sub;
     const bool vprob = lane_in && b < b1;
     const bool valid = vprob && p < k;
-    const double f = valid ? (double)f_raw : 0.0;
-    uint64_t F = (vprob && mask_in) ? (m_raw & all & ~pinned0) : 0ull;
-    prefetch(b0 + (g + gstride) * P + sub);
+    const double f = (double)f_next;
+    uint64_t F = vprob ? (m_next & all & ~pinned0) : 0ull;
+    {
+      const int64_t bn = b0 + (g + gstride) * P + sub;
+      f_next = (lane_in && bn < b1 && p < k) ? R[bn * ldr + p] : 0.0f;
+      m_next = (lane_in && bn < b1 && mask_in) ? mask_in[bn] : 0ull;
+    }
     uint64_t pinned = pinned0;
     bool warm = F != 0;
     int alpha = 3, beta = k + 1, rounds = 0, since = 0;
@@ -175,35 +174,6 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
 #pragma unroll
       for (int q = 0; q < K; ++q) z += Gi[q * K + p] * rfv[wave][base + q];
       wave_lds_sync();
-    }
-    // Start set = every unpinned index U, and z >= 0 on U: the first round
-    // would take the inverse form with no pivots, read out x_U = z_U, find
-    // no infeasible index and stop.  The problem ends here with that x, set,
-    // round count and solve statistics.
-    {
-      const uint64_t U = all & ~pinned0;
-      const bool cand = inv_ok && vprob && U != 0ull && F == U;
-      const bool inU = (U >> p) & 1ull;
-      const uint64_t nb = __ballot(cand && valid && inU && z < 0.0);
-      uint64_t mine;
-      if constexpr (K == 64) {
-        mine = nb;
-      } else {
-        mine = (nb >> base) & (bit64(K) - 1ull);
-      }
-      if (cand && mine == 0ull) {
-        done = true;
-        xfin = inU ? z : 0.0;
-        rounds = 1;
-        if (p == 0 && lane_in) {
-          const unsigned long long nf = (unsigned long long)__popcll(U);
-          ++c_rounds;
-          ++c_solves;
-          c_f1 += nf;
-          c_f2 += nf * nf;
-          c_f3 += nf * nf * nf;
-        }
-      }
     }
 
     while (__ballot(!done) != 0) {
