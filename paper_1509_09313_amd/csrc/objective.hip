@@ -92,7 +92,7 @@ __global__ __launch_bounds__(64) void k_obj_dense(int64_t m, int64_t n, int k, c
   const int64_t ntiles = (n + 31) / 32;
   const int64_t tend = (tile0 + kObjColTiles < ntiles) ? tile0 + kObjColTiles : ntiles;
   // the next tile's H^T operands and A entries are loaded while the current
-  // tile is reduced (acc[v] = (W Ht^T)[r0 + ii][c0 + i], ii = (v&3) + 8(v>>2) + 4h)
+  // tile is reduced (A, read once, with non-temporal loads) (acc[v] = (W Ht^T)[r0 + ii][c0 + i], ii = (v&3) + 8(v>>2) + 4h)
   float hn[NS], an[16];
 #define NMF_OBJ_LOAD(TL)                                                              \
   do {                                                                                \
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64) void k_obj_dense(int64_t m, int64_t n, int k, c
     }                                                                                 \
     _Pragma("unroll") for (int v_ = 0; v_ < 16; ++v_) {                               \
       const int64_t row_ = r0 + (v_ & 3) + 8 * (v_ >> 2) + 4 * h;                     \
-      an[v_] = (jn_ < n && row_ < m) ? A[row_ * lda + jn_] : 0.0f;                    \
+      an[v_] = (jn_ < n && row_ < m) ? __builtin_nontemporal_load(A + row_ * lda + jn_) : 0.0f; \
     }                                                                                 \
   } while (0)
   if (tile0 < tend) NMF_OBJ_LOAD(tile0);

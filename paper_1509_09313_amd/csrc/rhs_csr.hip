@@ -63,8 +63,10 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t rows, int k, const int64_t
     for (int64_t p = rowptr[i]; p < p1; p += kBlock) {
       const int64_t e0 = p + l < p1 ? p + l : p1 - 1;
       const int64_t e1 = p + 64 + l < p1 ? p + 64 + l : p1 - 1;
-      const int ca = colidx[e0], cb = colidx[e1];
-      const float va = vals[e0], vb = vals[e1];
+      // the index stream is read once: non-temporal loads leave the L2 to
+      // the gathered rows of Y
+      const int ca = __builtin_nontemporal_load(colidx + e0), cb = __builtin_nontemporal_load(colidx + e1);
+      const float va = __builtin_nontemporal_load(vals + e0), vb = __builtin_nontemporal_load(vals + e1);
 #pragma unroll
       for (int h = 0; h < kBlock / kChunk; ++h) {
         const int64_t q = p + h * kChunk;
