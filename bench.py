@@ -52,7 +52,7 @@ def parse(argv=None):
     ap.add_argument("--k", type=int, default=30)
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--cold-iters", type=int, default=5)
-    ap.add_argument("--train-steps", type=int, default=50)
+    ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--train-batch", type=int, default=1024)
     ap.add_argument("--collect-stride", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
