@@ -87,6 +87,21 @@ def test_sparse_small_trajectory():
     assert abs(obj[0] - ref["r_full"][-1]) <= RTOL_OBJ
 
 
+def test_sparse_small_warm_prev_matches_cold():
+    """Starting each NNLS from the previous iteration's passive set leaves the
+    sparse trajectory on the oracle's (the solutions are unique) and saves
+    BPP rounds; the padded SpMM factor copy is exercised at k = 50."""
+    w = C.WORKLOADS["c3s"]
+    rp, ci, va = C.sparse_csr(w.seed, w.m, w.n, w.density, inst=w.inst)
+    rpt, cit, vat = C.csr_transpose(w.m, w.n, rp, ci, va)
+    W0, H0 = C.init_w(w.seed, w.m, w.k, inst=w.inst), C.init_ht(w.seed, w.n, w.k, inst=w.inst)
+    ref = oracle.anls(w.k, W0, H0, w.iters, csr=(rp, ci, va), csr_t=(rpt, cit, vat), shape=(w.m, w.n))
+    M = L.Matrix(csr=(cuda(rp), cuda(ci), cuda(va)), csr_t=(cuda(rpt), cuda(cit), cuda(vat)), shape=(w.m, w.n))
+    W, Ht, st = run_gpu(M, w.k, W0, H0, w.iters, warm=L.NMF_WARM_PREV, warm_cap=50)
+    check_traj(st, ref, "sparse 2000x1500 warm-prev")
+    assert sum(s["bpp_w"][0] for s in st[1:]) < ref["rounds_w"][1:].sum()
+
+
 def test_dense_planted_scaled_trajectory():
     w = C.WORKLOADS["c2s"]
     iters = 10
