@@ -100,6 +100,50 @@ def test_video_full_products_sampled(video):
     print(f"accumulation chains: fp32 side H {tf}, bf16x3 side W {L.rhs_dense_chain(0, m, n, k, 1)} side H {tb}")
 
 
+@pytest.mark.parametrize("k", [50, 64])
+def test_video_full_products_wide_k(video, k):
+    """The two-tile (k > 32) product kernels at full size: sampled rows of
+    A H^T and whole columns of A^T W, FP32 and BF16x3, within the chain
+    bounds, for k = 50 (ragged second tile) and k = 64."""
+    seed, m, n = video["seed"], video["m"], video["n"]
+    A, M = video["A"], video["M"]
+    bt, btt = M.tiled
+    W0, Ht0 = gen.init_factors(seed, m, n, k)
+    # the seeded device generator's factors (bit-identical to the host
+    # recipe, checked here on sampled rows) are the oracle's inputs too
+    W0h, H0h = W0.cpu().numpy(), C.init_ht(seed, n, k)
+    assert np.array_equal(Ht0.cpu().numpy(), H0h)
+    probe = np.array([0, 1, 4097, m - 1])
+    assert np.array_equal(W0h[probe], C.init_w(seed, m, k, rows=probe))
+    rng = np.random.default_rng(12)
+    rows = np.concatenate([[0, m - 1], rng.choice(m, 30, replace=False)])
+    Ar = C.video_rows(seed, n, rows)
+    absY = np.abs(H0h.astype(np.float64))
+    for prec, tag in ((L.NMF_F32, "fp32"), (L.NMF_BF16X3, "bf16x3")):
+        if prec == L.NMF_F32:
+            R = L.nmf_rhs_dense(L.NMF_SIDE_W, A, Ht0)
+            ref, slack = oracle.rhs_dense_w(Ar, H0h), 1.01
+        else:
+            R = L.nmf_rhs_dense(L.NMF_SIDE_W, None, Ht0, prec=prec, B_bf16=bt, m=m, n=n)
+            ref, slack = osplit.rhs_w(Ar, H0h), 1.02
+        t = L.rhs_dense_chain(L.NMF_SIDE_W, m, n, k, prec)
+        check_bound(R[cuda(rows)].cpu().numpy(), ref, slack * t * U32 * (np.abs(Ar.astype(np.float64)) @ absY),
+                    f"R_W {tag} k={k}")
+    cols = np.array([0, 777, n - 1])
+    Ac = C.video_rows(seed, n, np.arange(m), cols)
+    absW = np.abs(W0h.astype(np.float64))
+    for prec, tag in ((L.NMF_F32, "fp32"), (L.NMF_BF16X3, "bf16x3")):
+        if prec == L.NMF_F32:
+            R = L.nmf_rhs_dense(L.NMF_SIDE_H, A, W0)
+            ref, slack = oracle.rhs_dense_h(Ac, W0h), 1.01
+        else:
+            R = L.nmf_rhs_dense(L.NMF_SIDE_H, None, W0, prec=prec, B_bf16=btt, m=m, n=n)
+            ref, slack = osplit.rhs_h(Ac, W0h), 1.02
+        t = L.rhs_dense_chain(L.NMF_SIDE_H, m, n, k, prec)
+        check_bound(R[cuda(cols)].cpu().numpy(), ref, slack * t * U32 * (np.abs(Ac.astype(np.float64)).T @ absW),
+                    f"R_H {tag} k={k}")
+
+
 def test_video_full_bpp_launch():
     """The W-side NNLS launch at its full size (10^6 problems, k = 30) on
     host-made problems shaped like the workload's (G from the initial Ht,
