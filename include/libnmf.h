@@ -59,6 +59,11 @@ extern "C" {
 #define NMF_WARM_PREV 1     /* start from the previous iteration's passive set */
 #define NMF_WARM_LEARNED 2  /* start from the warm-start network's prediction */
 
+/* local NLS solver of Algorithm 1 (nmf_opts.solver, nmf_local_update) */
+#define NMF_SOLVER_BPP 0    /* block principal pivoting (the exact NNLS solution) */
+#define NMF_SOLVER_HALS 1   /* one HALS sweep, Eq. halsupdate */
+#define NMF_SOLVER_MU 2     /* one multiplicative update, Eq. muupdate */
+
 /* per-problem BPP status bits */
 #define NMF_BPP_WARM_FALLBACK 1  /* warm start restarted cold after warm_cap rounds */
 #define NMF_BPP_CAPPED 2         /* KKT still violated after max_rounds; x clamped to >= 0 */
@@ -183,6 +188,20 @@ int nmf_mlp_train(int k, float* params, float* adam_m, float* adam_v, const floa
                   int64_t nsamples, const int64_t* order, int steps, int batch, float lr, int64_t step0,
                   double* loss_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- other local updates (Section "Nonnegative Least Squares") ------------
+ * One MU (Eq. muupdate) or HALS (Eq. halsupdate) update of every row x of X
+ * (rows x k FP32, ldx >= k, device, in place) from G (k x k FP64, the Gram
+ * matrix of the other factor) and R (rows x k FP32, ldr >= k: A H^T rows for
+ * the rows of W, (W^T A)^T rows for the rows of H^T):
+ *   NMF_SOLVER_MU:   x_j <- x_j r_j / (x^T G)_j, all j from the old x;
+ *                    x_j <- 0 where (x^T G)_j <= 0;
+ *   NMF_SOLVER_HALS: for i = 0 .. k-1 in order,
+ *                    x_i <- max(0, r_i - sum_{l != i} G_li x_l) / G_ii.
+ * Indices with G_ii <= 1e-14 max_l G_ll are set to 0.  FP64 arithmetic, one
+ * rounding to FP32 per entry.  Enqueued on `stream`. */
+int nmf_local_update(int solver, int k, int64_t rows, const double* G, const float* R, int64_t ldr, float* X,
+                     int64_t ldx, void* stream);
+
 /* ---- the data matrix ------------------------------------------------------- */
 typedef struct nmf_matrix {
   int kind;                 /* NMF_DENSE or NMF_CSR */
@@ -255,6 +274,11 @@ typedef struct nmf_opts {
    * For the product phases the pair brackets the main product kernel only. */
   void** phase_events;
   int phase_events_cap;
+  /* the local update of both half-steps: NMF_SOLVER_BPP (0, the default of a
+   * zeroed struct), NMF_SOLVER_HALS or NMF_SOLVER_MU.  HALS and MU start from
+   * the current W and Ht and need warm = NMF_WARM_COLD and collect = 0; the
+   * BPP counters of nmf_iter_stats stay zero for them. */
+  int solver;
 } nmf_opts;
 
 /* phases of one iteration, for nmf_opts.phase_events */

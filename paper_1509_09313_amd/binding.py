@@ -19,6 +19,7 @@ NMF_SIDE_W, NMF_SIDE_H = 0, 1
 NMF_DENSE, NMF_CSR = 0, 1
 NMF_OBJ_DIRECT, NMF_OBJ_TRACE = 0, 1
 NMF_WARM_COLD, NMF_WARM_PREV, NMF_WARM_LEARNED = 0, 1, 2
+NMF_SOLVER_BPP, NMF_SOLVER_HALS, NMF_SOLVER_MU = 0, 1, 2
 NMF_BPP_WARM_FALLBACK, NMF_BPP_CAPPED, NMF_BPP_PINNED, NMF_BPP_SINGULAR = 1, 2, 4, 8
 NMF_BPP_COUNTERS = 6
 NMF_BATCH_RESET = 1
@@ -54,7 +55,7 @@ class nmf_opts(ctypes.Structure):
                 ("collect", ci), ("collect_stride_w", ci), ("collect_stride_h", ci),
                 ("coll_phi_w", vp), ("coll_mask_w", vp), ("coll_cap_w", i64), ("coll_off_w", i64),
                 ("coll_phi_h", vp), ("coll_mask_h", vp), ("coll_cap_h", i64), ("coll_off_h", i64),
-                ("phase_events", ctypes.POINTER(vp)), ("phase_events_cap", ci)]
+                ("phase_events", ctypes.POINTER(vp)), ("phase_events_cap", ci), ("solver", ci)]
 
 
 class nmf_iter_stats(ctypes.Structure):
@@ -105,6 +106,7 @@ def lib():
             "nmf_split_bf16": ([i64, i64, vp, i64, ci, vp, vp], ci),
             "nmf_rhs_csr": ([i64, i64, ci, vp, vp, vp, vp, i64, vp, i64, vp], ci),
             "nnls_bpp_batched": ([ci, i64, vp, vp, i64, vp, i64, vp, vp, vp, vp, ci, ci, vp, vp], ci),
+            "nmf_local_update": ([ci, ci, i64, vp, vp, i64, vp, i64, vp], ci),
             "nmf_fro2_workspace_bytes": ([M, sz], ci),
             "nmf_fro2": ([M, vp, vp, ctypes.c_size_t, vp], ci),
             "nmf_objective_workspace_bytes": ([M, ci, ci, sz], ci),
@@ -243,6 +245,17 @@ def nmf_rhs_csr(rowptr, colidx, vals, Y, rows, cols, R=None):
     return R
 
 
+def nmf_local_update(solver, G, R, X):
+    """One HALS or MU update of the rows of X (rows x k float32, in place)
+    from G (k x k float64) and R (rows x k float32).  Returns X."""
+    _dev(G, torch.float64, "G")
+    _dev(R, torch.float32, "R")
+    _dev(X, torch.float32, "X")
+    rows, k = X.shape
+    _check(lib().nmf_local_update(solver, k, rows, _ptr(G), _ptr(R), _ld(R), _ptr(X), _ld(X), _stream()))
+    return X
+
+
 def nnls_bpp_batched(G, R, X=None, mask_in=None, mask_out=None, rounds=None, status=None, max_rounds=100,
                      warm_cap=8, counters=None):
     """Rows of R (batch x k, float32) against G (k x k, float64).  Returns
@@ -320,9 +333,10 @@ def nmf_objective(M: Matrix, W, Ht, mode=NMF_OBJ_DIRECT, G_W=None, G_H=None, R_H
 
 
 def make_opts(prec=NMF_F32, warm=NMF_WARM_COLD, max_rounds=100, warm_cap=8, trace=True, reset_masks=True,
-              net_w=None, net_h=None):
+              net_w=None, net_h=None, solver=NMF_SOLVER_BPP):
     o = nmf_opts()
     o.prec, o.warm, o.max_rounds, o.warm_cap = prec, warm, max_rounds, warm_cap
+    o.solver = solver
     o.trace_objective, o.reset_masks = int(trace), int(reset_masks)
     o.net_w = None if net_w is None else net_w.data_ptr()
     o.net_h = None if net_h is None else net_h.data_ptr()

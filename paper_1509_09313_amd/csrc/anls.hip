@@ -1,6 +1,7 @@
 // Algorithm 1 (ANLS) on one GPU: for each iteration
 //   G_H = H H^T (from Ht), R_W = A H^T, W = BPP(G_H, R_W)       (W update)
 //   G_W = W^T W,           R_H = A^T W, Ht = BPP(G_W, R_H)      (H update)
+// (or one HALS / MU update of W and Ht in place of BPP: nmf_opts.solver)
 // with the optional trace-form objective after each half-step.  At p = 1 the
 // collectives of Algorithm 3 vanish and these are exactly its local steps.
 // Everything is enqueued on one stream; nothing synchronises with the host.
@@ -126,6 +127,10 @@ int check_opts(const nmf_matrix* A, const nmf_opts* o) {
   if (o->warm == NMF_WARM_LEARNED && (!o->net_w || !o->net_h))
     return nmf::fail(NMF_EINVAL, "nmf_anls: learned warm start needs both networks");
   if (o->max_rounds < 1 || o->warm_cap < 1) return nmf::fail(NMF_EINVAL, "nmf_anls: max_rounds/warm_cap < 1");
+  if (o->solver != NMF_SOLVER_BPP && o->solver != NMF_SOLVER_HALS && o->solver != NMF_SOLVER_MU)
+    return nmf::fail(NMF_EINVAL, "nmf_anls: bad solver");
+  if (o->solver != NMF_SOLVER_BPP && (o->warm != NMF_WARM_COLD || o->collect))
+    return nmf::fail(NMF_EINVAL, "nmf_anls: HALS and MU take no warm start and collect no samples");
   if (o->collect) {
     if (o->collect_stride_w < 1 || o->collect_stride_h < 1 || !o->coll_phi_w || !o->coll_mask_w ||
         !o->coll_phi_h || !o->coll_mask_h || o->coll_off_w < 0 || o->coll_off_h < 0)
@@ -256,10 +261,14 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
       NMF_TRY(nmf::mlp_infer_launch(k, m, P.GH, P.RW, k, o->net_w, P.MW, P.infer_w, s));
     rec(ev(t, NMF_PH_INFER_W, 1));
     rec(ev(t, NMF_PH_BPP_W, 0));
-    NMF_TRY(nmf::bpp_launch(k, m, P.GH, P.RW, k, W, k, warm ? P.MW : nullptr, P.MW, nullptr, P.status, o->max_rounds,
-                            o->warm_cap, st ? st->bpp_w : nullptr, s));
+    if (o->solver == NMF_SOLVER_BPP) {
+      NMF_TRY(nmf::bpp_launch(k, m, P.GH, P.RW, k, W, k, warm ? P.MW : nullptr, P.MW, nullptr, P.status,
+                              o->max_rounds, o->warm_cap, st ? st->bpp_w : nullptr, s));
+    } else {
+      NMF_TRY(nmf::local_update_launch(o->solver, k, m, P.GH, P.RW, k, W, k, s));
+    }
     rec(ev(t, NMF_PH_BPP_W, 1));
-    if (st) NMF_TRY(count_status(m, P.status, st, s));
+    if (st && o->solver == NMF_SOLVER_BPP) NMF_TRY(count_status(m, P.status, st, s));
     if (o->collect)
       NMF_TRY(collect(k, m, o->collect_stride_w, P.GH, P.RW, P.MW, o->coll_phi_w, o->coll_mask_w, o->coll_cap_w,
                       &hc[0], s));
@@ -282,10 +291,14 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
       NMF_TRY(nmf::mlp_infer_launch(k, n, P.GW, P.RH, k, o->net_h, P.MH, P.infer_h, s));
     rec(ev(t, NMF_PH_INFER_H, 1));
     rec(ev(t, NMF_PH_BPP_H, 0));
-    NMF_TRY(nmf::bpp_launch(k, n, P.GW, P.RH, k, Ht, k, warm ? P.MH : nullptr, P.MH, nullptr, P.status, o->max_rounds,
-                            o->warm_cap, st ? st->bpp_h : nullptr, s));
+    if (o->solver == NMF_SOLVER_BPP) {
+      NMF_TRY(nmf::bpp_launch(k, n, P.GW, P.RH, k, Ht, k, warm ? P.MH : nullptr, P.MH, nullptr, P.status,
+                              o->max_rounds, o->warm_cap, st ? st->bpp_h : nullptr, s));
+    } else {
+      NMF_TRY(nmf::local_update_launch(o->solver, k, n, P.GW, P.RH, k, Ht, k, s));
+    }
     rec(ev(t, NMF_PH_BPP_H, 1));
-    if (st) NMF_TRY(count_status(n, P.status, st, s));
+    if (st && o->solver == NMF_SOLVER_BPP) NMF_TRY(count_status(n, P.status, st, s));
     if (o->collect)
       NMF_TRY(collect(k, n, o->collect_stride_h, P.GW, P.RH, P.MH, o->coll_phi_h, o->coll_mask_h, o->coll_cap_h,
                       &hc[1], s));

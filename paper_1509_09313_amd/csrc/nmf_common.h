@@ -67,6 +67,9 @@ int rhs_csr_launch(int64_t rows, int64_t cols, int k, const int64_t* rowptr, con
                    const float* vals, const float* Y, int64_t ldy, float* R, int64_t ldr, float* ypad,
                    hipStream_t s);
 
+int local_update_launch(int solver, int k, int64_t rows, const double* G, const float* R, int64_t ldr, float* X,
+                        int64_t ldx, hipStream_t s);
+
 int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X,
                int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds,
                uint8_t* status, int max_rounds, int warm_cap, uint64_t* counters, hipStream_t s);

@@ -66,6 +66,11 @@ def test_host_validation_without_gpu(L):
     assert lib.nmf_split_bf16_bytes(300, 70, 1) == 2 * 128 * 320 * 2
     # CSR: ld < k
     assert lib.nmf_rhs_csr(4, 4, 8, G, G, G, G, 4, G, 8, None) == L.NMF_EINVAL
+    # HALS / MU: bad solver, k, ld; ANLS with HALS takes no warm start
+    assert lib.nmf_local_update(0, 8, 10, G, G, 8, G, 8, None) == L.NMF_EINVAL
+    assert lib.nmf_local_update(L.NMF_SOLVER_HALS, 0, 10, G, G, 8, G, 8, None) == L.NMF_EINVAL
+    assert lib.nmf_local_update(L.NMF_SOLVER_MU, 8, 10, G, G, 4, G, 8, None) == L.NMF_EINVAL
+    assert lib.nmf_local_update(L.NMF_SOLVER_MU, 8, 10, None, G, 8, G, 8, None) == L.NMF_EINVAL
     # objective and ANLS: null matrix / bad opts
     assert lib.nmf_objective(None, 4, G, G, 0, None, None, None, G, G, 1 << 20, None) == L.NMF_EINVAL
     M = L.nmf_matrix()
@@ -76,6 +81,12 @@ def test_host_validation_without_gpu(L):
     assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
     o = L.make_opts(warm=L.NMF_WARM_LEARNED)
     assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
+    o = L.make_opts(solver=L.NMF_SOLVER_HALS, warm=L.NMF_WARM_PREV)
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
+    o = L.make_opts(solver=7)
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
+    o = L.make_opts(solver=L.NMF_SOLVER_MU)
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_OK
     o = L.make_opts()
     assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_OK
     assert nb.value > 0
