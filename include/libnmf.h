@@ -190,15 +190,19 @@ int nmf_mlp_train(int k, float* params, float* adam_m, float* adam_v, const floa
 
 /* ---- other local updates (Section "Nonnegative Least Squares") ------------
  * One MU (Eq. muupdate) or HALS (Eq. halsupdate) update of every row x of X
- * (rows x k FP32, ldx >= k, device, in place) from G (k x k FP64, the Gram
- * matrix of the other factor) and R (rows x k FP32, ldr >= k: A H^T rows for
+ * (rows x k FP32, ldx >= k, device, in place) from G (k x k FP64, row-major,
+ * device: the Gram matrix of the other factor, which must be symmetric; the
+ * kernel reads column l of G as row l) and R (rows x k FP32, ldr >= k: A H^T rows for
  * the rows of W, (W^T A)^T rows for the rows of H^T):
  *   NMF_SOLVER_MU:   x_j <- x_j r_j / (x^T G)_j, all j from the old x;
  *                    x_j <- 0 where (x^T G)_j <= 0;
  *   NMF_SOLVER_HALS: for i = 0 .. k-1 in order,
  *                    x_i <- max(0, r_i - sum_{l != i} G_li x_l) / G_ii.
  * Indices with G_ii <= 1e-14 max_l G_ll are set to 0.  FP64 arithmetic, one
- * rounding to FP32 per entry.  Enqueued on `stream`. */
+ * rounding to FP32 per entry (HALS divides by G_ii as a product with its
+ * FP64 reciprocal; partial sums in a fixed order of four).  Enqueued on
+ * `stream`; X may not overlap R.  NMF_EINVAL for another solver, k outside
+ * [1, 64], rows < 0, ldr or ldx < k, or a null pointer with rows > 0. */
 int nmf_local_update(int solver, int k, int64_t rows, const double* G, const float* R, int64_t ldr, float* X,
                      int64_t ldx, void* stream);
 

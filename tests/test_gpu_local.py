@@ -31,6 +31,7 @@ def problem(rng, k, rows, pin=None):
     if pin is not None:
         C_[:, pin] = 0.0
     G = C_.T @ C_
+    G = 0.5 * (G + G.T)                                           # exactly symmetric, like nmf_gram's
     R = (rng.uniform(0.0, 1.0, (rows, C_.shape[0])) @ C_).astype(np.float32)
     R[: rows // 3] -= np.float32(0.5) * R[: rows // 3].mean()     # some negative entries
     X = rng.uniform(0.0, 1.0, (rows, k)).astype(np.float32)
@@ -107,3 +108,16 @@ def test_anls_local_trajectory(solver):
         assert worst <= 1e-5
         assert abs(direct - ref["r_full"][-1]) <= 1e-5
         assert all(s["bpp_w"][0] == 0 for s in dec)
+
+
+@pytest.mark.parametrize("solver", ["hals", "mu"])
+def test_local_update_every_k(solver):
+    """Each k in 1..64 is its own compiled kernel: all of them, 131 rows (two
+    full 64-row tiles and a ragged one), against the oracle."""
+    for k in range(1, 65):
+        rng = np.random.default_rng(5000 + k)
+        G, R, X = problem(rng, k, 131, k - 1 if k > 3 else None)
+        ref = local.UPDATES[solver](G, R.astype(np.float64), X.astype(np.float64))
+        Xg = cuda(X)
+        L.nmf_local_update(SOLVERS[solver], cuda(G), cuda(R), Xg)
+        check(Xg.cpu().numpy(), ref, f"{solver} k={k}")
