@@ -36,6 +36,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ANLS-BPP iters/sec at matched rel. objective (learned+BF16 vs plain FP32)"
 GOLDEN = os.path.join(ROOT, "tests", "golden", "video_1e6x2400_k30_oracle.json")
+LOCAL_GOLDEN = os.path.join(ROOT, "tests", "golden", "video_1e6x2400_k30_local_oracle.json")
+KSWEEP_GOLDEN = os.path.join(ROOT, "tests", "golden", "video_1e6x2400_ksweep_oracle.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 HBM_PEAK_GBS = 8000.0
@@ -59,8 +61,12 @@ def parse(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched measurement")
+    ap.add_argument("--no-local", action="store_true", help="skip the HALS / MU local-solver measurement")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--pmc", action="store_true", help="copy calibration + product kernels only (for rocprofv3 --pmc)")
+    ap.add_argument("--ksweep", action="store_true",
+                    help="time per iteration and its MM / NLS / Gram split for k = 10..50 on the video workload")
+    ap.add_argument("--ksweep-iters", type=int, default=10)
     ap.add_argument("--sparse", action="store_true",
                     help="the CSR workload (207360 x 138240): alone, or with --pmc its SpMM kernels too")
     return ap.parse_args(argv)
@@ -277,6 +283,58 @@ def cpu_baseline(bench, seconds):
             "seconds_per_iter_full": per_iter}
 
 
+def local_forms(bench):
+    """Algorithm 1 with the HALS and MU local updates (Eq. halsupdate,
+    Eq. muupdate) on the same workload: BF16x3 right-hand sides, FP64 Gram,
+    the update in FP64; `iters` iterations from the same seeded W, H per step.
+    The final relative objective is compared with the FP64 oracle's."""
+    import numpy as np
+
+    a, L = bench.a, bench.L
+    ref = None
+    if os.path.exists(LOCAL_GOLDEN) and (a.m, a.n, a.k, a.iters) == (1_000_000, 2_400, 30, 50):
+        with open(LOCAL_GOLDEN) as fh:
+            ref = json.load(fh)
+    out = {}
+    for name, solver in (("hals", L.NMF_SOLVER_HALS), ("mu", L.NMF_SOLVER_MU)):
+        run = L.Anls(bench.M, a.k, L.make_opts(prec=L.NMF_BF16X3, trace=True, solver=solver))
+        stats = L.new_stats(a.iters)
+
+        def step(timer=None):
+            bench.W.copy_(bench.W0)
+            bench.Ht.copy_(bench.Ht0)
+            if timer:
+                timer.attach(run.opts)
+            run.run(bench.W, bench.Ht, a.iters, stats)
+            if timer:
+                timer.detach(run.opts)
+
+        t = timed(step, a.steps, a.warmup)
+        r = bench.final_r()
+        tm = L.PhaseTimer(a.iters)
+        step(tm)
+        bench.torch.cuda.synchronize()
+        ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
+        tm.close()
+        o = None if ref is None else ref[name]["r_full"][-1]
+        # the W-side update streams R (read) and W (read and written): 12 k bytes per row
+        alg = 12.0 * a.k * a.m
+        gbs = alg / (ph["bpp_w"] * 1e-3) / 1e9
+        out[name] = {"iters_per_s": a.iters * a.steps / t, "ms_per_step": t / a.steps * 1e3, "final_r": r,
+                     "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o),
+                     "update_ms_per_iter": {"w": ph["bpp_w"], "h": ph["bpp_h"]},
+                     "update_w_roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                                           "frac": gbs / 8000.0, "algorithmic_bytes_per_launch": alg,
+                                           "fp64_tflops": 2.0 * a.k * a.k * a.m / (ph["bpp_w"] * 1e-3) / 1e12},
+                     "phase_ms_per_iter": ph}
+        print(f"# {name}: {out[name]['ms_per_step']:.1f} ms/step, final r {r:.8f}", file=sys.stderr, flush=True)
+    out["note"] = ("the update phase is reported in the bpp_* slots of phase_ms_per_iter; "
+                   "r after the same number of iterations differs between solvers (BPP solves each NNLS exactly)")
+    return out
+
+
+KS = (10, 20, 30, 40, 50)
+
 BATCH_GOLDEN = os.path.join(ROOT, "tests", "golden", "batched_256_oracle.json")
 
 
@@ -441,6 +499,77 @@ def sparse_mode(a):
     print(json.dumps({"sparse": res}))
 
 
+def ksweep_mode(a):
+    """The rank axis of the paper's algorithmic comparison on one GPU: for
+    k = 10, 20, 30, 40, 50 on the video-like workload, iterations per second
+    and the per-iteration time split into the paper's local tasks (MM: the
+    two right-hand-side products, NLS: the two local solves, Gram: the two
+    Gram matrices; Section "Time Breakdown"), for Algorithm 1 with BPP
+    (FP32 and BF16x3 products), HALS and MU.  `ksweep_iters` iterations per
+    step from the seeded start; the BPP forms' relative objective is compared
+    with the FP64 oracle's after the same number of iterations."""
+    import numpy as np
+    import torch
+
+    from nmf_inputs import configs as C
+    from nmf_inputs import device as gen
+    from paper_1509_09313_amd import binding as L
+    m, n, T = a.m, a.n, a.ksweep_iters
+    seed = C.seed_for(5)
+    A = gen.video(seed, m, n)
+    M = L.Matrix(dense=A)
+    M.add_split()
+    ref = None
+    if os.path.exists(KSWEEP_GOLDEN) and (m, n) == (1_000_000, 2_400):
+        with open(KSWEEP_GOLDEN) as fh:
+            ref = json.load(fh)
+        if ref["iterations"] != T:
+            ref = None
+    forms = (("bpp_fp32", dict(prec=L.NMF_F32)), ("bpp_bf16x3", dict(prec=L.NMF_BF16X3)),
+             ("hals_bf16x3", dict(prec=L.NMF_BF16X3, solver=L.NMF_SOLVER_HALS)),
+             ("mu_bf16x3", dict(prec=L.NMF_BF16X3, solver=L.NMF_SOLVER_MU)))
+    out = {"workload": f"video-like dense {m}x{n}, {T} iterations per step from the seeded start, cold BPP",
+           "ks": list(KS), "forms": {}}
+    for name, kw in forms:
+        rows = []
+        for k in KS:
+            W0, Ht0 = gen.init_factors(seed, m, n, k)
+            W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
+            run = L.Anls(M, k, L.make_opts(trace=True, reset_masks=True, **kw))
+            stats = L.new_stats(T)
+
+            def step(timer=None):
+                W.copy_(W0)
+                Ht.copy_(Ht0)
+                if timer:
+                    timer.attach(run.opts)
+                run.run(W, Ht, T, stats)
+                if timer:
+                    timer.detach(run.opts)
+
+            t = timed(step, a.steps, a.warmup)
+            r = float(L.nmf_objective(M, W, Ht)[0])
+            tm = L.PhaseTimer(T)
+            step(tm)
+            torch.cuda.synchronize()
+            ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
+            tm.close()
+            o = None
+            if ref is not None and name.startswith("bpp"):
+                o = ref["k"][str(k)]["r_full"][-1]
+            ms = t / (a.steps * T) * 1e3
+            split = {"MM": ph["rhs_w"] + ph["rhs_h"], "NLS": ph["bpp_w"] + ph["bpp_h"],
+                     "Gram": ph["gram_w"] + ph["gram_h"]}
+            split["rest"] = ms - sum(split.values())
+            rows.append({"k": k, "iters_per_s": 1e3 / ms, "ms_per_iter": ms, "split_ms": split, "final_r": r,
+                         "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o)})
+            print(f"# {name} k={k}: {ms:.2f} ms/iter (MM {split['MM']:.2f}, NLS {split['NLS']:.2f}, "
+                  f"Gram {split['Gram']:.2f}), r {r:.8f}", file=sys.stderr, flush=True)
+            del run, W, Ht, W0, Ht0
+        out["forms"][name] = rows
+    print(json.dumps({"ksweep": out}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -452,6 +581,9 @@ def main():
         return
     if a.sparse:
         sparse_mode(a)
+        return
+    if a.ksweep:
+        ksweep_mode(a)
         return
     import numpy as np
     b = Bench(a)
@@ -499,6 +631,10 @@ def main():
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(b, a.cpu_seconds)
 
+    loc = None
+    if not a.no_local:
+        loc = local_forms(b)
+
     bat = None
     if not a.no_batched:
         bat = batched(a)
@@ -537,6 +673,7 @@ def main():
         "one_time_split_s": b.t_split,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "local_solvers": loc,
         "batched": bat,
     }
     for pair in timers:

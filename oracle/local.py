@@ -78,3 +78,47 @@ def anls(solver, k, W0, Ht0, T, *, dense):
         Ht = upd(GW, A.T @ W, Ht)
         r_full[t] = np.linalg.norm(A - W @ Ht.T) / nA
     return dict(W=W, Ht=Ht, r_half=r_half, r_full=r_full)
+
+
+def _products(A, Ht, W, chunk):
+    """A @ Ht and A^T @ W in FP64 over row blocks of a (possibly FP32) A."""
+    m = A.shape[0]
+    RW = None if Ht is None else np.empty((m, Ht.shape[1]))
+    RH = None if W is None else np.zeros((A.shape[1], W.shape[1]))
+    for r0 in range(0, m, chunk):
+        blk = np.asarray(A[r0:r0 + chunk], dtype=np.float64)
+        if RW is not None:
+            RW[r0:r0 + chunk] = blk @ Ht
+        if RH is not None:
+            RH += blk.T @ W[r0:r0 + chunk]
+    return RW, RH
+
+
+def anls_trace(solver, k, W0, Ht0, T, A, chunk=20_000):
+    """Algorithm 1 with the MU or HALS update on a large dense A (m x n, any
+    float dtype, read in row blocks), FP64 throughout.  The relative objective
+    comes from the expansion ||A - W H||^2 = ||A||^2 - 2 <R, X> + <G_W, G_H>
+    with the right-hand sides R of the half-step (the trace form, no m x n
+    temporary).  Returns W, Ht, r_half, r_full."""
+    upd = UPDATES[solver]
+    W = np.asarray(W0, dtype=np.float64).copy()
+    Ht = np.asarray(Ht0, dtype=np.float64).copy()
+    fro2 = 0.0
+    for r0 in range(0, A.shape[0], chunk):
+        fro2 += float(np.sum(np.asarray(A[r0:r0 + chunk], dtype=np.float64) ** 2))
+    r_half, r_full = np.zeros(T), np.zeros(T)
+
+    def rel(R, X, GW, GH):
+        return np.sqrt(max(fro2 - 2.0 * float(np.sum(R * X)) + float(np.sum(GW * GH)), 0.0) / fro2)
+
+    for t in range(T):
+        GH = oracle.gram(Ht)
+        RW, _ = _products(A, Ht, None, chunk)
+        W = upd(GH, RW, W)
+        GW = oracle.gram(W)
+        r_half[t] = rel(RW, W, GW, GH)
+        _, RH = _products(A, None, W, chunk)
+        Ht = upd(GW, RH, Ht)
+        GH = oracle.gram(Ht)
+        r_full[t] = rel(RH, Ht, GW, GH)
+    return dict(W=W, Ht=Ht, r_half=r_half, r_full=r_full, fro2=fro2)

@@ -114,7 +114,6 @@ __global__ __launch_bounds__(64) void k_local(int64_t rows, const double* __rest
                                               int64_t ldx) {
   constexpr int P = K | 1;  // tile pitch in floats
   __shared__ float T[64 * P];
-  __shared__ double inv_d[K];
   const GPtr G0 = (GPtr)Gin;
   const int lane = threadIdx.x;
 
@@ -122,10 +121,15 @@ __global__ __launch_bounds__(64) void k_local(int64_t rows, const double* __rest
 #pragma unroll
   for (int q = 0; q < K; ++q) dmax = fmax(dmax, G0[q * K + q]);
   const double thr = 1e-14 * dmax;
+  // lane j < K holds 1 / G_jj (0 marks a pinned index); the sweeps fetch it
+  // with readlane, keeping LDS (and its wait counter, shared with the scalar
+  // loads) out of them
+  double inv_mine = 0.0;
   if (lane < K) {
     const double g = Gin[lane * K + lane];
-    inv_d[lane] = g > thr ? 1.0 / g : 0.0;  // 0 marks a pinned index
+    inv_mine = g > thr ? 1.0 / g : 0.0;
   }
+  const int inv_lo = __double2loint(inv_mine), inv_hi = __double2hiint(inv_mine);
 
   const int64_t ntiles = (rows + 63) / 64;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -150,10 +154,16 @@ __global__ __launch_bounds__(64) void k_local(int64_t rows, const double* __rest
         constexpr int i = I;
         double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < K; ++q)
+        for (int q = 0; q < K; ++q) {
           if (q != i) a[q & 3] = fma(G[i * K + q], x[q], a[q & 3]);
+          // at most one 8-double burst of G ahead of its use: scheduling the
+          // loads of later rows early runs out of SGPRs
+          if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
         const double s = (double)Tl[i] - ((a[0] + a[1]) + (a[2] + a[3]));
-        x[i] = fmax(s, 0.0) * inv_d[i];
+        const double inv = __hiloint2double(__builtin_amdgcn_readlane(inv_hi, i),
+                                            __builtin_amdgcn_readlane(inv_lo, i));
+        x[i] = fmax(s, 0.0) * inv;
       });
       static_for<K>([&](auto C) __attribute__((always_inline)) { Tw[C] = (float)x[C]; });
     } else {
@@ -164,7 +174,9 @@ __global__ __launch_bounds__(64) void k_local(int64_t rows, const double* __rest
         for (int q = 0; q < K; ++q) a[q & 3] = fma(G[j * K + q], x[q], a[q & 3]);
         const double d = (a[0] + a[1]) + (a[2] + a[3]);
         const double rj = (double)Tl[j];
-        Tw[j] = (inv_d[j] > 0.0 && d > 0.0) ? (float)(x[j] * rj / d) : 0.0f;
+        const double inv = __hiloint2double(__builtin_amdgcn_readlane(inv_hi, j),
+                                            __builtin_amdgcn_readlane(inv_lo, j));
+        Tw[j] = (inv > 0.0 && d > 0.0) ? (float)(x[j] * rj / d) : 0.0f;
       });
     }
     __syncthreads();

@@ -356,3 +356,54 @@ def test_csr_gather_beyond_4gib():
     torch.cuda.empty_cache()
     ref = oracle.rhs_csr(rp, inv.astype(np.int32), va, Ysub).astype(np.float32)
     assert np.array_equal(R, ref)
+
+
+@pytest.mark.parametrize("solver", ["hals", "mu"])
+def test_video_full_local_trajectory(video, solver):
+    """Algorithm 1 with the HALS or MU update at full size, 50 iterations with
+    BF16x3 right-hand sides (the benchmark's form), against the stored FP64
+    oracle run (tests/golden/video_1e6x2400_k30_local_oracle.json): the trace
+    objective after every half-step and the direct one at the end."""
+    path = os.path.join(HERE, "golden", "video_1e6x2400_k30_local_oracle.json")
+    with open(path) as fh:
+        ref = json.load(fh)[solver]
+    k, M = video["k"], video["M"]
+    code = {"hals": L.NMF_SOLVER_HALS, "mu": L.NMF_SOLVER_MU}[solver]
+    W, Ht = video["W0"].clone(), video["Ht0"].clone()
+    T = len(ref["r_full"])
+    st = L.new_stats(T)
+    L.Anls(M, k, L.make_opts(prec=L.NMF_BF16X3, trace=True, solver=code)).run(W, Ht, T, st)
+    torch.cuda.synchronize()
+    dec = L.decode_stats(st)
+    dh = np.abs(np.array([s["r_half"] for s in dec]) - ref["r_half"])
+    df = np.abs(np.array([s["r_full"] for s in dec]) - ref["r_full"])
+    direct = float(L.nmf_objective(M, W, Ht)[0])
+    print(f"{solver}: r_50 {ref['r_full'][-1]:.10f}, max |dr| trace {max(dh.max(), df.max()):.2e}, "
+          f"direct {abs(direct - ref['r_full'][-1]):.2e}")
+    assert max(dh.max(), df.max()) <= TOL_R
+    assert abs(direct - ref["r_full"][-1]) <= TOL_R
+
+
+@pytest.mark.parametrize("k", [10, 20, 40, 50])
+def test_video_full_ksweep(video, k):
+    """The ranks of the paper's algorithmic comparison (k = 10..50; k = 30 is
+    covered above) at full size: 10 cold-BPP iterations with FP32 and BF16x3
+    right-hand sides against the stored FP64 oracle runs
+    (tests/golden/video_1e6x2400_ksweep_oracle.json), every half-step."""
+    with open(os.path.join(HERE, "golden", "video_1e6x2400_ksweep_oracle.json")) as fh:
+        gold = json.load(fh)
+    ref, T = gold["k"][str(k)], gold["iterations"]
+    M = video["M"]
+    W0, Ht0 = gen.init_factors(video["seed"], video["m"], video["n"], k)
+    for prec, label in ((L.NMF_F32, "fp32"), (L.NMF_BF16X3, "bf16x3")):
+        W, Ht, st = _run(M, k, W0, Ht0, T, prec=prec)
+        rf = np.array([s["r_full"] for s in st])
+        rh = np.array([s["r_half"] for s in st])
+        dr = max(np.max(np.abs(rf - ref["r_full"])), np.max(np.abs(rh - ref["r_half"])))
+        r_direct = float(L.nmf_objective(M, W, Ht)[0])
+        print(f"k={k} {label}: max |dr| over {T} iterations {dr:.2e}; final direct r {r_direct:.10f} "
+              f"oracle {ref['r_full'][-1]:.10f}")
+        assert dr <= TOL_R
+        assert abs(r_direct - ref["r_full"][-1]) <= TOL_R
+        assert all(s["capped"] == 0 for s in st)
+        del W, Ht

@@ -113,3 +113,20 @@ def test_alg1_objective_is_monotone(solver):
     seq = np.ravel(np.column_stack([out["r_half"], out["r_full"]]))
     assert np.all(np.diff(seq) <= 1e-12)
     assert seq[-1] < seq[0]
+
+
+@pytest.mark.parametrize("solver", ["mu", "hals"])
+def test_trace_form_loop_equals_direct(solver):
+    """The row-chunked, trace-form Algorithm 1 gives the direct loop's
+    factors and objectives (the expansion of ||A - WH||^2 is exact up to
+    rounding)."""
+    rng = np.random.default_rng(600)
+    m, n, k = 130, 70, 6
+    A = (rng.uniform(0.0, 1.0, (m, 4)) @ rng.uniform(0.0, 1.0, (4, n))).astype(np.float32)
+    W0, H0 = rng.uniform(0.0, 1.0, (m, k)), rng.uniform(0.0, 1.0, (n, k))
+    a = local.anls(solver, k, W0, H0, 6, dense=A)
+    b = local.anls_trace(solver, k, W0, H0, 6, A, chunk=37)
+    assert np.allclose(a["W"], b["W"], rtol=1e-12, atol=1e-14)
+    assert np.allclose(a["Ht"], b["Ht"], rtol=1e-12, atol=1e-14)
+    assert np.allclose(a["r_half"], b["r_half"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(a["r_full"], b["r_full"], rtol=1e-9, atol=1e-12)
