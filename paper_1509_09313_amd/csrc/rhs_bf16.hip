@@ -141,51 +141,50 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
 #pragma unroll
   for (int tt = 0; tt < NT; ++tt) acc[tt] = v16f{};
 
-  // staging registers for the next chunk (explicit scalars: no arrays to
-  // keep them out of scratch)
-  uint4 bh0, bh1, bh2, bh3, bl0, bl1, bl2, bl3, yh0, yl0, yh1, yl1;
-#define NMF_LOAD_CHUNK(KC)                                                                  \
-  do {                                                                                      \
-    const int64_t c0_ = (KC) * kTC;                                                         \
-    const uint16_t* ph_ = Bh + (int64_t)(t >> 3) * Cp + c0_ + 8 * (t & 7);                  \
-    const uint16_t* pl_ = ph_ + Rp * Cp;                                                    \
-    const int64_t rs_ = 32 * Cp; /* 256 threads cover 32 rows */                            \
-    bh0 = load_stream(ph_);                                                                 \
-    bh1 = load_stream(ph_ + rs_);                                                           \
-    bh2 = load_stream(ph_ + 2 * rs_);                                                       \
-    bh3 = load_stream(ph_ + 3 * rs_);                                                       \
-    bl0 = load_stream(pl_);                                                                 \
-    bl1 = load_stream(pl_ + rs_);                                                           \
-    bl2 = load_stream(pl_ + 2 * rs_);                                                       \
-    bl3 = load_stream(pl_ + 3 * rs_);                                                       \
-    const int64_t yo_ = (int64_t)(t >> 3) * ldt + c0_ + 8 * (t & 7);                        \
-    yh0 = *reinterpret_cast<const uint4*>(Yth + yo_);                                       \
-    yl0 = *reinterpret_cast<const uint4*>(Ytl + yo_);                                       \
-    if (NT == 2) {                                                                          \
-      yh1 = *reinterpret_cast<const uint4*>(Yth + yo_ + 32 * ldt);                          \
-      yl1 = *reinterpret_cast<const uint4*>(Ytl + yo_ + 32 * ldt);                          \
-    }                                                                                       \
-  } while (0)
-  const int so = (t >> 3) * kBPitch + 8 * (t & 7);
-  if (kc0 < kc1) NMF_LOAD_CHUNK(kc0);
-  for (int64_t kc = kc0; kc < kc1; ++kc) {
-    __syncthreads();
-    *reinterpret_cast<uint4*>(&Bs[0][so]) = bh0;
-    *reinterpret_cast<uint4*>(&Bs[0][so + 32 * kBPitch]) = bh1;
-    *reinterpret_cast<uint4*>(&Bs[0][so + 64 * kBPitch]) = bh2;
-    *reinterpret_cast<uint4*>(&Bs[0][so + 96 * kBPitch]) = bh3;
-    *reinterpret_cast<uint4*>(&Bs[1][so]) = bl0;
-    *reinterpret_cast<uint4*>(&Bs[1][so + 32 * kBPitch]) = bl1;
-    *reinterpret_cast<uint4*>(&Bs[1][so + 64 * kBPitch]) = bl2;
-    *reinterpret_cast<uint4*>(&Bs[1][so + 96 * kBPitch]) = bl3;
-    *reinterpret_cast<uint4*>(&Ys[0][so]) = yh0;
-    *reinterpret_cast<uint4*>(&Ys[1][so]) = yl0;
+  // A chunk in flight: the staging registers of one 64-column chunk (explicit
+  // members: no arrays, which keeps them out of scratch).
+  struct Stage {
+    uint4 bh0, bh1, bh2, bh3, bl0, bl1, bl2, bl3, yh0, yl0, yh1, yl1;
+  };
+  auto load = [&](Stage& S, int64_t kc) __attribute__((always_inline)) {
+    const int64_t c0 = kc * kTC;
+    const uint16_t* ph = Bh + (int64_t)(t >> 3) * Cp + c0 + 8 * (t & 7);
+    const uint16_t* pl = ph + Rp * Cp;
+    const int64_t rs = 32 * Cp;  // 256 threads cover 32 rows
+    S.bh0 = load_stream(ph);
+    S.bh1 = load_stream(ph + rs);
+    S.bh2 = load_stream(ph + 2 * rs);
+    S.bh3 = load_stream(ph + 3 * rs);
+    S.bl0 = load_stream(pl);
+    S.bl1 = load_stream(pl + rs);
+    S.bl2 = load_stream(pl + 2 * rs);
+    S.bl3 = load_stream(pl + 3 * rs);
+    const int64_t yo = (int64_t)(t >> 3) * ldt + c0 + 8 * (t & 7);
+    S.yh0 = *reinterpret_cast<const uint4*>(Yth + yo);
+    S.yl0 = *reinterpret_cast<const uint4*>(Ytl + yo);
     if (NT == 2) {
-      *reinterpret_cast<uint4*>(&Ys[0][so + 32 * kBPitch]) = yh1;
-      *reinterpret_cast<uint4*>(&Ys[1][so + 32 * kBPitch]) = yl1;
+      S.yh1 = *reinterpret_cast<const uint4*>(Yth + yo + 32 * ldt);
+      S.yl1 = *reinterpret_cast<const uint4*>(Ytl + yo + 32 * ldt);
     }
-    __syncthreads();
-    if (kc + 1 < kc1) NMF_LOAD_CHUNK(kc + 1);
+  };
+  const int so = (t >> 3) * kBPitch + 8 * (t & 7);
+  auto store = [&](const Stage& S) __attribute__((always_inline)) {
+    *reinterpret_cast<uint4*>(&Bs[0][so]) = S.bh0;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 32 * kBPitch]) = S.bh1;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 64 * kBPitch]) = S.bh2;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 96 * kBPitch]) = S.bh3;
+    *reinterpret_cast<uint4*>(&Bs[1][so]) = S.bl0;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 32 * kBPitch]) = S.bl1;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 64 * kBPitch]) = S.bl2;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 96 * kBPitch]) = S.bl3;
+    *reinterpret_cast<uint4*>(&Ys[0][so]) = S.yh0;
+    *reinterpret_cast<uint4*>(&Ys[1][so]) = S.yl0;
+    if (NT == 2) {
+      *reinterpret_cast<uint4*>(&Ys[0][so + 32 * kBPitch]) = S.yh1;
+      *reinterpret_cast<uint4*>(&Ys[1][so + 32 * kBPitch]) = S.yl1;
+    }
+  };
+  auto compute = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < kBTK / 16; ++s) {
       const int off = 16 * s + 8 * h;
@@ -200,8 +199,56 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
         acc[tt] = mfma_bf16(yh, bl, acc[tt]);
       }
     }
+  };
+  if (kc1 - kc0 >= 4) {
+    // Two chunks in flight: the loads of chunk c + 2 are issued while chunk
+    // c + 1 is still arriving.  The main loop's loads are unconditional, so
+    // each wait is for the older set only; the last two or three chunks
+    // follow in straight-line code.
+    Stage A, B;
+    load(A, kc0);
+    __builtin_amdgcn_sched_barrier(0);  // same issue order as in the loop
+    load(B, kc0 + 1);
+    int64_t kc = kc0;
+    for (; kc + 3 < kc1; kc += 2) {
+      __syncthreads();
+      store(A);
+      __syncthreads();
+      load(A, kc + 2);
+      compute();
+      __syncthreads();
+      store(B);
+      __syncthreads();
+      load(B, kc + 3);
+      compute();
+    }
+    const bool three = kc + 2 < kc1;
+    __syncthreads();
+    store(A);
+    __syncthreads();
+    if (three) load(A, kc + 2);
+    compute();
+    __syncthreads();
+    store(B);
+    __syncthreads();
+    compute();
+    if (three) {
+      __syncthreads();
+      store(A);
+      __syncthreads();
+      compute();
+    }
+  } else {
+    Stage A;
+    if (kc0 < kc1) load(A, kc0);
+    for (int64_t kc = kc0; kc < kc1; ++kc) {
+      __syncthreads();
+      store(A);
+      __syncthreads();
+      if (kc + 1 < kc1) load(A, kc + 1);
+      compute();
+    }
   }
-#undef NMF_LOAD_CHUNK
   const int64_t r = row0 + 32 * w + j;
   if (r < rows) {
 #pragma unroll
