@@ -249,15 +249,25 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
       compute();
     }
   }
-  const int64_t r = row0 + 32 * w + j;
-  if (r < rows) {
+  // The finished tile goes out through LDS (the B staging buffer, idle now)
+  // so that the stores cover whole rows (straight from the MFMA layout each
+  // store instruction touches 32 rows with 8 bytes each), and the stores are
+  // non-temporal: written while A streams in, ordinary stores slow the read
+  // stream more (10^6 x 2400, k = 30: 1.715 ms scattered, 1.688 through LDS,
+  // 1.620 through LDS non-temporal; 1.417 with no output at all).
+  constexpr int OP = KP + 1;  // odd pitch: conflict-free column writes
+  static_assert(kBTM * OP * sizeof(float) <= sizeof(Bs), "output tile exceeds the staging buffer");
+  float* O = reinterpret_cast<float*>(&Bs[0][0]);
+  __syncthreads();
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt)
+  for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int c = 32 * tt + (v & 3) + 8 * (v >> 2) + 4 * h;
-        if (c < k) out[r * ldp + c] = acc[tt][v];
-      }
+    for (int v = 0; v < 16; ++v) O[(32 * w + j) * OP + 32 * tt + (v & 3) + 8 * (v >> 2) + 4 * h] = acc[tt][v];
+  __syncthreads();
+  const int nr = rows - row0 < kBTM ? (int)(rows - row0) : kBTM;
+  for (int e = t; e < nr * k; e += 256) {
+    const int row = e / k, c = e - row * k;
+    __builtin_nontemporal_store(O[row * OP + c], &out[(row0 + row) * ldp + c]);
   }
   __syncthreads();
 }
