@@ -272,13 +272,13 @@ from oracle import split as osplit  # noqa: E402
 
 @pytest.mark.parametrize("m,n,k,pad", [(200, 150, 5, 0), (257, 131, 30, 0), (129, 1000, 50, 1), (33, 4097, 64, 0),
                                        (1000, 999, 33, 3), (70000, 300, 30, 0), (20000, 2400, 30, 8),
-                                       (40000, 700, 50, 0)])
+                                       (40000, 700, 50, 0), (70000, 700, 30, 0)])
 def test_rhs_dense_bf16x3(m, n, k, pad):
     """Bound: each of the 3L BF16 products is exact in FP32 and the chain is
     accumulated in FP32, so |R - oracle| <= 3 L 2^-24 (|A||Y|) (1 + small).
-    The sizes give blocks with 1, 2, 4, 5, 12 and 13 chunks of the contraction
-    (the single-staging loop, and the two-staging main loop with its two- and
-    three-chunk tails), for one and two 32-column tiles of k."""
+    The sizes give blocks with 1 to 13 chunks of the contraction: the single-
+    staging loop, and the two-staging main loop with its two- and three-chunk
+    tails, for one and two 32-column tiles of k."""
     rng = np.random.default_rng(3 * m + n + k)
     A = rng.uniform(0.0, 1.0, (m, n)).astype(np.float32)
     Ht = rng.uniform(0.0, 1.0, (n, k)).astype(np.float32)
