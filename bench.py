@@ -561,10 +561,14 @@ def ksweep_mode(a):
             split = {"MM": ph["rhs_w"] + ph["rhs_h"], "NLS": ph["bpp_w"] + ph["bpp_h"],
                      "Gram": ph["gram_w"] + ph["gram_h"]}
             split["rest"] = ms - sum(split.values())
+            # algorithmic bytes of the two products: A once each, the other factor read, R written
+            mm_bytes = 2.0 * (4.0 * m * n + 4.0 * n * k + 4.0 * m * k)
+            mm_gbs = mm_bytes / (split["MM"] * 1e-3) / 1e9
             rows.append({"k": k, "iters_per_s": 1e3 / ms, "ms_per_iter": ms, "split_ms": split, "final_r": r,
-                         "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o)})
-            print(f"# {name} k={k}: {ms:.2f} ms/iter (MM {split['MM']:.2f}, NLS {split['NLS']:.2f}, "
-                  f"Gram {split['Gram']:.2f}), r {r:.8f}", file=sys.stderr, flush=True)
+                         "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o),
+                         "mm_GBps": mm_gbs, "mm_hbm_frac": mm_gbs / 8000.0})
+            print(f"# {name} k={k}: {ms:.2f} ms/iter (MM {split['MM']:.2f} at {mm_gbs:.0f} GB/s, "
+                  f"NLS {split['NLS']:.2f}, Gram {split['Gram']:.2f}), r {r:.8f}", file=sys.stderr, flush=True)
             del run, W, Ht, W0, Ht0
         out["forms"][name] = rows
     print(json.dumps({"ksweep": out}))
