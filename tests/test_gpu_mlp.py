@@ -99,7 +99,7 @@ def test_predict_matches_oracle(k):
 
 
 def test_learned_warm_start_in_anls():
-    """Train the W- and H-side networks on samples collected by the driver,
+    """Train the W- and H-side networks on samples collected by nmf_anls_iter,
     then run with the learned warm start: the trajectory matches the cold
     oracle (the warm start cannot change the unique solutions) and needs fewer
     solves than cold."""
