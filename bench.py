@@ -64,6 +64,8 @@ def parse(argv=None):
     ap.add_argument("--no-local", action="store_true", help="skip the HALS / MU local-solver measurement")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--pmc", action="store_true", help="copy calibration + product kernels only (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-bpp", action="store_true",
+                    help="batched BPP from cold and exact start sets at a mid-run state (for rocprofv3 --pmc)")
     ap.add_argument("--ksweep", action="store_true",
                     help="time per iteration and its MM / NLS / Gram split for k = 10..50 on the video workload")
     ap.add_argument("--ksweep-iters", type=int, default=10)
@@ -441,6 +443,34 @@ def pmc_mode(a):
     print(json.dumps({"pmc": "done", "copy_bytes": 2 * src.numel() * 4}))
 
 
+def pmc_bpp_mode(a):
+    """For rocprofv3 counter collection on the NNLS kernel: the state after 6
+    BF16x3 iterations of Algorithm 1 from the seeded start (W side: G = H H^T,
+    R = A H^T), then batched BPP three times from a cold start and three times
+    from the exact final passive sets, alternating."""
+    import torch
+
+    from nmf_inputs import configs as C
+    from nmf_inputs import device as gen
+    from paper_1509_09313_amd import binding as L
+    m, n, k = a.m, a.n, a.k
+    seed = C.seed_for(5)
+    A = gen.video(seed, m, n)
+    W0, Ht0 = gen.init_factors(seed, m, n, k)
+    M = L.Matrix(dense=A, split=True)
+    W, Ht = W0.clone(), Ht0.clone()
+    L.Anls(M, k, L.make_opts(prec=L.NMF_BF16X3)).run(W, Ht, 6)
+    G = L.nmf_gram(Ht)
+    R = L.nmf_rhs_dense(L.NMF_SIDE_W, None, Ht, prec=L.NMF_BF16X3, B_bf16=M.tiled[0], m=m, n=n)
+    X = torch.empty_like(W)
+    _, mask, _, _ = L.nnls_bpp_batched(G, R, X)
+    for _ in range(3):
+        L.nnls_bpp_batched(G, R, X)
+        L.nnls_bpp_batched(G, R, X, mask_in=mask)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_bpp": "done", "problems": m, "k": k}))
+
+
 def sparse_mode(a):
     """The CSR workload at full size: plain FP32 SpMM right-hand sides, FP64
     Gram and BPP, `iters` iterations per step from the seeded start (cold
@@ -582,6 +612,9 @@ def main():
         sys.exit(2)
     if a.pmc:
         pmc_mode(a)
+        return
+    if a.pmc_bpp:
+        pmc_bpp_mode(a)
         return
     if a.sparse:
         sparse_mode(a)
