@@ -66,6 +66,8 @@ def parse(argv=None):
     ap.add_argument("--pmc", action="store_true", help="copy calibration + product kernels only (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-bpp", action="store_true",
                     help="batched BPP from cold and exact start sets at a mid-run state (for rocprofv3 --pmc)")
+    ap.add_argument("--dense", action="store_true",
+                    help="the dense planted workload at full size (172800 x 115200, k = 50, 30 iterations)")
     ap.add_argument("--ksweep", action="store_true",
                     help="time per iteration and its MM / NLS / Gram split for k = 10..50 on the video workload")
     ap.add_argument("--ksweep-iters", type=int, default=10)
@@ -471,6 +473,72 @@ def pmc_bpp_mode(a):
     print(json.dumps({"pmc_bpp": "done", "problems": m, "k": k}))
 
 
+def dense_mode(a):
+    """The dense planted workload at full size (172,800 x 115,200, rank-50
+    U[0,1) factors plus 0.01 U[0,1) noise; A is 79.6 GB in FP32), k = 50, 30
+    cold-BPP iterations per step: plain FP32 products, then BF16x3 products
+    from the padded planes of A and A^T (159 GB more, made after the FP32
+    form).  Reports iterations/s, the phase split, the products' rate (HBM
+    bytes and FP32 MFMA flops) and the final relative objective of each form
+    (the two must agree within 1e-5; the FP64 oracle cannot run this size, the
+    sampled full-size tests check it instead)."""
+    import numpy as np
+    import torch
+
+    from nmf_inputs import configs as C
+    from nmf_inputs import device as gen
+    from paper_1509_09313_amd import binding as L
+    seed, m, n, k, T = C.seed_for(2), 172_800, 115_200, 50, 30
+    t0 = time.perf_counter()
+    A = gen.planted(seed, m, n, k)
+    W0, Ht0 = gen.init_factors(seed, m, n, k)
+    M = L.Matrix(dense=A)
+    torch.cuda.synchronize()
+    print(f"# dense inputs: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
+    prod_bytes = 2.0 * (4.0 * m * n + 4.0 * n * k + 4.0 * m * k)
+    prod_flops = 2.0 * 2.0 * m * n * k
+
+    def form(prec):
+        run = L.Anls(M, k, L.make_opts(prec=prec, trace=True, reset_masks=True))
+        stats = L.new_stats(T)
+
+        def step(timer=None):
+            W.copy_(W0)
+            Ht.copy_(Ht0)
+            if timer:
+                timer.attach(run.opts)
+            run.run(W, Ht, T, stats)
+            if timer:
+                timer.detach(run.opts)
+
+        t = timed(step, a.steps, a.warmup)
+        tm = L.PhaseTimer(T)
+        step(tm)
+        torch.cuda.synchronize()
+        ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
+        tm.close()
+        r = float(L.nmf_objective(M, W, Ht)[0])
+        mm = (ph["rhs_w"] + ph["rhs_h"]) * 1e-3
+        st = L.decode_stats(stats)
+        out = {"iters_per_s": T * a.steps / t, "ms_per_iter": t / (a.steps * T) * 1e3, "final_r": r,
+               "phase_ms_per_iter": ph, "products_GBps": prod_bytes / mm / 1e9,
+               "products_hbm_frac": prod_bytes / mm / 8e12,
+               "products_fp32_mfma_TFLOPs": prod_flops / mm / 1e12, "capped": int(sum(s["capped"] for s in st))}
+        print(f"# dense {'fp32' if prec == L.NMF_F32 else 'bf16x3'}: {out['ms_per_iter']:.2f} ms/iter, "
+              f"products {out['products_GBps']:.0f} GB/s, r {r:.8f}", file=sys.stderr, flush=True)
+        return out
+
+    res = {"workload": f"planted dense {m}x{n} (rank 50 U[0,1) factors + 0.01 U[0,1) noise), k={k}, {T} cold-BPP "
+                       f"iterations per step from the seeded start"}
+    res["fp32"] = form(L.NMF_F32)
+    M.add_split()
+    torch.cuda.synchronize()
+    res["bf16x3"] = form(L.NMF_BF16X3)
+    res["abs_dr_bf16x3_vs_fp32"] = abs(res["bf16x3"]["final_r"] - res["fp32"]["final_r"])
+    print(json.dumps({"dense": res}))
+
+
 def sparse_mode(a):
     """The CSR workload at full size: plain FP32 SpMM right-hand sides, FP64
     Gram and BPP, `iters` iterations per step from the seeded start (cold
@@ -621,6 +689,9 @@ def main():
         return
     if a.ksweep:
         ksweep_mode(a)
+        return
+    if a.dense:
+        dense_mode(a)
         return
     import numpy as np
     b = Bench(a)
