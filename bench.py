@@ -321,6 +321,9 @@ def local_forms(bench):
         ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
         tm.close()
         o = None if ref is None else ref[name]["r_full"][-1]
+        # the FP64 oracle's own time for the same 50 iterations, recorded when the stored run was
+        # written (8 host threads of the machine that wrote it, not this one)
+        o_s = None if ref is None else ref[name]["oracle_seconds"] / a.iters
         # the W-side update streams R (read) and W (read and written): 12 k bytes per row
         alg = 12.0 * a.k * a.m
         gbs = alg / (ph["bpp_w"] * 1e-3) / 1e9
@@ -330,6 +333,7 @@ def local_forms(bench):
                      "update_w_roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
                                            "frac": gbs / 8000.0, "algorithmic_bytes_per_launch": alg,
                                            "fp64_tflops": 2.0 * a.k * a.k * a.m / (ph["bpp_w"] * 1e-3) / 1e12},
+                     "oracle_s_per_iter_recorded": o_s,
                      "phase_ms_per_iter": ph}
         print(f"# {name}: {out[name]['ms_per_step']:.1f} ms/step, final r {r:.8f}", file=sys.stderr, flush=True)
     out["note"] = ("the update phase is reported in the bpp_* slots of phase_ms_per_iter; "
@@ -652,9 +656,12 @@ def ksweep_mode(a):
             torch.cuda.synchronize()
             ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
             tm.close()
-            o = None
+            o = o_s = None
             if ref is not None and name.startswith("bpp"):
                 o = ref["k"][str(k)]["r_full"][-1]
+                # the FP64 oracle's own time for these iterations, recorded when the stored run was
+                # written (on the machine that wrote it)
+                o_s = ref["k"][str(k)]["oracle_seconds"] / ref["iterations"]
             ms = t / (a.steps * T) * 1e3
             split = {"MM": ph["rhs_w"] + ph["rhs_h"], "NLS": ph["bpp_w"] + ph["bpp_h"],
                      "Gram": ph["gram_w"] + ph["gram_h"]}
@@ -664,7 +671,7 @@ def ksweep_mode(a):
             mm_gbs = mm_bytes / (split["MM"] * 1e-3) / 1e9
             rows.append({"k": k, "iters_per_s": 1e3 / ms, "ms_per_iter": ms, "split_ms": split, "final_r": r,
                          "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o),
-                         "mm_GBps": mm_gbs, "mm_hbm_frac": mm_gbs / 8000.0})
+                         "mm_GBps": mm_gbs, "mm_hbm_frac": mm_gbs / 8000.0, "oracle_s_per_iter_recorded": o_s})
             print(f"# {name} k={k}: {ms:.2f} ms/iter (MM {split['MM']:.2f} at {mm_gbs:.0f} GB/s, "
                   f"NLS {split['NLS']:.2f}, Gram {split['Gram']:.2f}), r {r:.8f}", file=sys.stderr, flush=True)
             del run, W, Ht, W0, Ht0
