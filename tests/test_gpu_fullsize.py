@@ -287,6 +287,22 @@ def test_planted_full_sampled():
         assert np.all(np.abs(Y[on]) <= bnd[on])
         assert np.all(Y[~on] >= -bnd[~on])
         assert st[0]["r_full"] <= st[0]["r_half"] + 1e-6 and st[0]["capped"] == 0
+        # BF16x3 products on the same rows and columns (the planes of A and
+        # A^T: 159 GB more), in the launch configuration of the benchmark's
+        # --dense form (split contraction, whole rounds of workgroups)
+        del M, W, Ht
+        M = L.Matrix(dense=A, split=True)
+        bt, btt = M.tiled
+        RWb = L.nmf_rhs_dense(L.NMF_SIDE_W, None, Ht0, prec=L.NMF_BF16X3, B_bf16=bt, m=m, n=n)
+        tb = L.rhs_dense_chain(L.NMF_SIDE_W, m, n, k, L.NMF_BF16X3)
+        check_bound(RWb[cuda(rows)].cpu().numpy(), osplit.rhs_w(Ar, H0h),
+                    1.02 * tb * U32 * (np.abs(Ar.astype(np.float64)) @ Ha), "R_W bf16x3")
+        RHb = L.nmf_rhs_dense(L.NMF_SIDE_H, None, W0, prec=L.NMF_BF16X3, B_bf16=btt, m=m, n=n)[cuda(cols)]
+        tbh = L.rhs_dense_chain(L.NMF_SIDE_H, m, n, k, L.NMF_BF16X3)
+        check_bound(RHb.cpu().numpy(), osplit.rhs_h(Ac, W0h),
+                    1.02 * tbh * U32 * (np.abs(Ac.astype(np.float64)).T @ np.abs(W0h.astype(np.float64))),
+                    "R_H bf16x3")
+        del M, RWb, RHb
     finally:
         del A
         torch.cuda.empty_cache()
