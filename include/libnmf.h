@@ -200,7 +200,8 @@ int nmf_mlp_train(int k, float* params, float* adam_m, float* adam_v, const floa
  *                    x_i <- max(0, r_i - sum_{l != i} G_li x_l) / G_ii.
  * Indices with G_ii <= 1e-14 max_l G_ll are set to 0.  FP64 arithmetic, one
  * rounding to FP32 per entry (HALS divides by G_ii as a product with its
- * FP64 reciprocal; partial sums in a fixed order of four).  Enqueued on
+ * FP64 reciprocal, MU by (x^T G)_j as a product with a Newton-refined
+ * reciprocal; partial sums in a fixed order of four).  Enqueued on
  * `stream`; X may not overlap R.  NMF_EINVAL for another solver, k outside
  * [1, 64], rows < 0, ldr or ldx < k, or a null pointer with rows > 0. */
 int nmf_local_update(int solver, int k, int64_t rows, const double* G, const float* R, int64_t ldr, float* X,

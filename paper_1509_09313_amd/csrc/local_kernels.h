@@ -176,7 +176,12 @@ __global__ __launch_bounds__(64) void k_local(int64_t rows, const double* __rest
         const double rj = (double)Tl[j];
         const double inv = __hiloint2double(__builtin_amdgcn_readlane(inv_hi, j),
                                             __builtin_amdgcn_readlane(inv_lo, j));
-        Tw[j] = (inv > 0.0 && d > 0.0) ? (float)(x[j] * rj / d) : 0.0f;
+        // 1 / d from the hardware estimate and two Newton steps y <- y (2 - d y)
+        // (each doubles the correct bits), in place of the division sequence
+        double y = __builtin_amdgcn_rcp(d);
+        y = fma(y, fma(-d, y, 1.0), y);
+        y = fma(y, fma(-d, y, 1.0), y);
+        Tw[j] = (inv > 0.0 && d > 0.0) ? (float)(x[j] * rj * y) : 0.0f;
       });
     }
     __syncthreads();
