@@ -317,11 +317,21 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
 #pragma unroll
         for (int q = 0; q < K; ++q) r[q] = Mrow[q * K + p];
         double rf = rf0, mypiv = 1.0;
+        // one problem per wavefront: its pivot set is the same in every lane,
+        // so the per-index skip test is a scalar branch on one uniform copy
+        uint64_t PU = 0;
+        if constexpr (P == 1)
+          PU = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(Pv >> 32)) << 32) |
+               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)Pv);
         {
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             const bool pj = (Pv >> j) & 1ull;
-            if (__ballot(pj) == 0) continue;
+            if constexpr (P == 1) {
+              if (!((PU >> j) & 1ull)) continue;
+            } else {
+              if (__ballot(pj) == 0) continue;
+            }
             colv[wave][lane] = r[j];
             rfv[wave][lane] = rf;
             wave_lds_sync();
