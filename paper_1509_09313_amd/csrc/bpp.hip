@@ -317,21 +317,19 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
 #pragma unroll
         for (int q = 0; q < K; ++q) r[q] = Mrow[q * K + p];
         double rf = rf0, mypiv = 1.0;
-        // one problem per wavefront: its pivot set is the same in every lane,
-        // so the per-index skip test is a scalar branch on one uniform copy
+        // The lanes of a problem hold the same pivot set, so the union over
+        // the wavefront's problems is the OR of lanes 0, K, 2K, ... (read into
+        // SGPRs), and the per-index skip test is a scalar branch.
         uint64_t PU = 0;
-        if constexpr (P == 1)
-          PU = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(Pv >> 32)) << 32) |
-               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)Pv);
+#pragma unroll
+        for (int sp = 0; sp < P; ++sp)
+          PU |= ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(Pv >> 32), sp * K) << 32) |
+                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)Pv, sp * K);
         {
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             const bool pj = (Pv >> j) & 1ull;
-            if constexpr (P == 1) {
-              if (!((PU >> j) & 1ull)) continue;
-            } else {
-              if (__ballot(pj) == 0) continue;
-            }
+            if (!((PU >> j) & 1ull)) continue;
             colv[wave][lane] = r[j];
             rfv[wave][lane] = rf;
             wave_lds_sync();
