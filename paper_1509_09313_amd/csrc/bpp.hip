@@ -347,7 +347,11 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
                 st |= NMF_BPP_SINGULAR;
               }
             }
-            const double inv = use ? 1.0 / piv : 0.0;
+            // 1 / piv: hardware estimate and two Newton steps y <- y (2 - piv y)
+            double inv = __builtin_amdgcn_rcp(piv);
+            inv = fma(inv, fma(-piv, inv, 1.0), inv);
+            inv = fma(inv, fma(-piv, inv, 1.0), inv);
+            inv = use ? inv : 0.0;
             const double mlt = (use && p != j) ? r[j] * inv : 0.0;
             if (use && p == j) mypiv = piv;
 #pragma unroll
