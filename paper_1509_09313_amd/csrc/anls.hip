@@ -8,7 +8,9 @@
 #include "nmf_common.h"
 
 namespace nmf {
-int trace_finish_launch(const double* fro2, const double* cross, const double* gdot, double* out, hipStream_t s);
+int trace_objective_launch(int64_t len, const float* a, const float* b, int k, const double* GW, const double* GH,
+                           const double* fro2, double* partial, int nblocks, double* out, double* r_copy,
+                           hipStream_t s);
 // warm-start network (mlp.hip)
 int mlp_infer_plan(int k, int64_t batch, Carver& c, void** scratch);
 int mlp_pack_launch(int k, const float* params, void* scratch, hipStream_t s);
@@ -50,10 +52,6 @@ __global__ void k_status_count(int64_t n, const uint8_t* __restrict__ status, un
   }
 }
 
-__global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
-}
-
 // Copies the sampled problems' final passive sets (b % stride == 0) to
 // positions base + b / stride of the sample buffer.
 __global__ void k_collect_masks(int64_t batch, int64_t stride, const uint64_t* __restrict__ masks,
@@ -76,8 +74,6 @@ struct Plan {
   int gblocks;
   void* rhs_w;
   void* rhs_h;
-  double* cross;
-  double* gdot;
   double* obj;
   double* dpart;
   int dblocks;
@@ -104,8 +100,6 @@ int plan_anls(const nmf_matrix* A, int k, const nmf_opts* o, nmf::Carver& c, Pla
     // line-aligned copy of the SpMM's factor (Ht, then W: one after the other)
     P->rhs_w = P->rhs_h = c.take<float>((size_t)mx * nmf::csr_pad_ld(k));
   }
-  P->cross = c.take<double>(1);
-  P->gdot = c.take<double>(1);
   P->obj = c.take<double>(4);
   nmf::dot_plan(mx * k, c, &P->dpart, &P->dblocks);
   P->infer_w = P->infer_h = nullptr;
@@ -276,10 +270,8 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     NMF_TRY(nmf::gram_launch(m, k, W, k, P.GW, P.gpart, P.gblocks, s));
     rec(ev(t, NMF_PH_GRAM_W, 1));
     if (st && o->trace_objective) {
-      NMF_TRY(nmf::dot_f32_launch(m * k, P.RW, W, P.cross, P.dpart, P.dblocks, s));
-      NMF_TRY(nmf::dot_f64_launch((int64_t)k * k, P.GW, P.GH, P.gdot, P.dpart, P.dblocks, s));
-      NMF_TRY(nmf::trace_finish_launch(A->fro2, P.cross, P.gdot, P.obj, s));
-      hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, s, P.obj, &st->r_half);
+      NMF_TRY(nmf::trace_objective_launch(m * k, P.RW, W, k, P.GW, P.GH, A->fro2, P.dpart, P.dblocks, P.obj,
+                                          &st->r_half, s));
     }
     // ---- H update: H = argmin ||A - W H||, from W^T W and W^T A
     {
@@ -307,10 +299,8 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     rec(ev(t, NMF_PH_GRAM_H, 1));
     rec(ev(t, NMF_PH_OTHER, 0));
     if (st && o->trace_objective) {
-      NMF_TRY(nmf::dot_f32_launch(n * k, P.RH, Ht, P.cross, P.dpart, P.dblocks, s));
-      NMF_TRY(nmf::dot_f64_launch((int64_t)k * k, P.GW, P.GH, P.gdot, P.dpart, P.dblocks, s));
-      NMF_TRY(nmf::trace_finish_launch(A->fro2, P.cross, P.gdot, P.obj, s));
-      hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, s, P.obj, &st->r_full);
+      NMF_TRY(nmf::trace_objective_launch(n * k, P.RH, Ht, k, P.GW, P.GH, A->fro2, P.dpart, P.dblocks, P.obj,
+                                          &st->r_full, s));
     }
     rec(ev(t, NMF_PH_OTHER, 1));
   }

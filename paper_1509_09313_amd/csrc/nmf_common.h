@@ -78,12 +78,10 @@ int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ld
 // it is safe inside captured graphs).
 int zero_f32(float* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t s);
 
-// Deterministic FP64 dot products  out[0] = sum_i a[i] * b[i]  over `len`
-// elements of two FP32 arrays (a, b) or FP64 arrays.
+// Deterministic FP64 dot product  out[0] = sum_i a[i] * b[i]  over `len`
+// elements of two FP32 arrays.
 int dot_plan(int64_t len, Carver& c, double** partial, int* nblocks);
 int dot_f32_launch(int64_t len, const float* a, const float* b, double* out, double* partial,
-                   int nblocks, hipStream_t s);
-int dot_f64_launch(int64_t len, const double* a, const double* b, double* out, double* partial,
                    int nblocks, hipStream_t s);
 
 // Kernel-level timing hook: when set (by the ANLS driver), the product

@@ -196,6 +196,39 @@ __global__ void k_obj_finish(int mode, const double* __restrict__ sums, const do
   out[2] = fro2;
 }
 
+// The trace expansion in one block: cross = the sum of the dot kernel's
+// per-block partials (fixed order), gdot = <G_W, G_H>_F over kk entries, then
+// out = {r, res2, fro2} with res2 = fro2 - 2 cross + gdot; r is also stored
+// to *r_copy when that is given.
+__global__ void k_trace_finish(int64_t nparts, const double* __restrict__ partial, int64_t kk,
+                               const double* __restrict__ GW, const double* __restrict__ GH,
+                               const double* __restrict__ fro2_in, double* __restrict__ out,
+                               double* __restrict__ r_copy) {
+  __shared__ double s[2][kRedThreads];
+  double c = 0.0, g = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += kRedThreads) c += partial[i];
+  for (int64_t i = threadIdx.x; i < kk; i += kRedThreads) g += GW[i] * GH[i];
+  s[0][threadIdx.x] = c;
+  s[1][threadIdx.x] = g;
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + off];
+      s[1][threadIdx.x] += s[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double fro2 = fro2_in[0];
+    const double res2 = fro2 - 2.0 * s[0][0] + s[1][0];
+    const double r = fro2 > 0.0 ? sqrt(fmax(res2, 0.0) / fro2) : 0.0;
+    out[0] = r;
+    out[1] = res2;
+    out[2] = fro2;
+    if (r_copy) r_copy[0] = r;
+  }
+}
+
 __global__ void k_zero_f32(float* __restrict__ p, int64_t rows, int64_t cols, int64_t ld) {
   const int64_t total = rows * cols;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -219,7 +252,6 @@ struct ObjPlan {
   double* GH = nullptr;
   double* gpart = nullptr;    // gram partials
   int gblocks = 0;
-  double* cross = nullptr;
   double* gdot = nullptr;
   double* dpart = nullptr;
   int dblocks = 0;
@@ -232,7 +264,6 @@ void dense_grid(int64_t m, int64_t n, int64_t* gx, int64_t* gy) {
 
 void plan_objective(const nmf_matrix* A, int k, int mode, nmf::Carver& c, ObjPlan* P) {
   P->sums = c.take<double>(4);
-  P->cross = c.take<double>(1);
   P->gdot = c.take<double>(1);
   if (mode == NMF_OBJ_DIRECT && A->kind == NMF_DENSE) {
     int64_t gx, gy;
@@ -296,17 +327,16 @@ int dot_f32_launch(int64_t len, const float* a, const float* b, double* out, dou
   return launch_status("dot reduce");
 }
 
-int dot_f64_launch(int64_t len, const double* a, const double* b, double* out, double* partial, int nblocks,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_dot<double>, dim3(nblocks), dim3(kRedThreads), 0, s, len, a, b, partial);
-  NMF_TRY(launch_status("dot f64"));
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(kRedThreads), 0, s, (int64_t)nblocks, 1, partial, out);
-  return launch_status("dot reduce");
-}
-
-// {r, res2, fro2} from the trace expansion; used by the ANLS driver too.
-int trace_finish_launch(const double* fro2, const double* cross, const double* gdot, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_obj_finish, dim3(1), dim3(64), 0, s, 1, nullptr, fro2, cross, gdot, out);
+// {r, res2, fro2} of the trace expansion, with cross = <a, b> over len FP32
+// elements (a = R, b = the factor just solved for) and the Gram inner product
+// <G_W, G_H>_F; used by the ANLS driver too.  Two launches.
+int trace_objective_launch(int64_t len, const float* a, const float* b, int k, const double* GW, const double* GH,
+                           const double* fro2, double* partial, int nblocks, double* out, double* r_copy,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_dot<float>, dim3(nblocks), dim3(kRedThreads), 0, s, len, a, b, partial);
+  NMF_TRY(launch_status("objective cross term"));
+  hipLaunchKernelGGL(k_trace_finish, dim3(1), dim3(kRedThreads), 0, s, (int64_t)nblocks, partial, (int64_t)k * k, GW,
+                     GH, fro2, out, r_copy);
   return launch_status("objective finish");
 }
 
@@ -370,9 +400,7 @@ extern "C" int nmf_objective(const nmf_matrix* A, int k, const float* W, const f
   const int64_t m = A->m, n = A->n;
 
   if (mode == NMF_OBJ_TRACE) {
-    NMF_TRY(nmf::dot_f32_launch(n * k, R_H, Ht, P.cross, P.dpart, P.dblocks, s));
-    NMF_TRY(nmf::dot_f64_launch((int64_t)k * k, G_W, G_H, P.gdot, P.dpart, P.dblocks, s));
-    return nmf::trace_finish_launch(A->fro2, P.cross, P.gdot, out, s);
+    return nmf::trace_objective_launch(n * k, R_H, Ht, k, G_W, G_H, A->fro2, P.dpart, P.dblocks, out, nullptr, s);
   }
   if (A->kind == NMF_DENSE) {
     int64_t gx, gy;
