@@ -221,6 +221,13 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
   // are known on the host
   int64_t hc[2] = {o->collect ? o->coll_off_w : 0, o->collect ? o->coll_off_h : 0};
 
+  if (stats && iters > 0) {  // every iteration's record starts from zero
+    const int64_t words = (int64_t)iters * (int64_t)(sizeof(nmf_iter_stats) / sizeof(uint64_t));
+    const int64_t blocks = nmf::cdiv(words, 256);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)(blocks > 1024 ? 1024 : blocks)), dim3(256), 0, s,
+                       reinterpret_cast<uint64_t*>(stats), words);
+    NMF_TRY(nmf::launch_status("zero stats"));
+  }
   NMF_TRY(nmf::gram_launch(n, k, Ht, k, P.GH, P.gpart, P.gblocks, s));
   if (o->warm == NMF_WARM_LEARNED) {
     NMF_TRY(nmf::mlp_pack_launch(k, o->net_w, P.infer_w, s));
@@ -240,11 +247,6 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
   };
   for (int t = 0; t < iters; ++t) {
     nmf_iter_stats* st = stats ? stats + t : nullptr;
-    if (st) {
-      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<uint64_t*>(st),
-                         (int64_t)(sizeof(nmf_iter_stats) / sizeof(uint64_t)));
-      NMF_TRY(nmf::launch_status("zero stats"));
-    }
     // ---- W update: W = argmin ||A - W H||, from H H^T and A H^T
     {
       MarkScope mark(ev(t, NMF_PH_RHS_W, 0), ev(t, NMF_PH_RHS_W, 1));
