@@ -69,32 +69,25 @@ __device__ __forceinline__ v16f mfma_bf16(v8bf a, v8bf b, v16f c) {
 }
 
 // Y (K x k FP32, ld ldy) -> transposed BF16 planes Yth, Ytl (KP x ldt), rows
-// i >= k and columns >= K zero.  One block per 64 rows of Y (from row K0, a
-// multiple of 64; ldt is a multiple of 64 and the planes are 4-byte aligned).
-// The block's rows are read as one flat run of k-wide rows (every lane busy),
-// and each lane writes two adjacent columns of a plane row as one 32-bit word.
+// i >= k and columns >= K zero.  One block per 64 rows of Y (from row K0).
 __device__ __forceinline__ void split_y_chunk(int64_t K, int k, int KP, const float* __restrict__ Y, int64_t ldy,
                                               uint16_t* __restrict__ Yth, uint16_t* __restrict__ Ytl, int64_t ldt,
                                               int64_t K0) {
   __shared__ float tile[64][65];
-  const int nrow = K - K0 >= 64 ? 64 : (K > K0 ? (int)(K - K0) : 0);
   __syncthreads();
-  const float* y0 = Y + K0 * ldy;
-  for (int e = threadIdx.x; e < nrow * k; e += 256) {
-    const int r = e / k, c = e - r * k;
-    tile[r][c] = y0[(int64_t)r * ldy + c];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int kk = e / 64, c = e - kk * 64;
+    tile[kk][c] = (K0 + kk < K && c < k) ? Y[(K0 + kk) * ldy + c] : 0.0f;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < KP * 32; e += 256) {
-    const int i = e >> 5, kk = 2 * (e & 31);
+  for (int e = threadIdx.x; e < KP * 64; e += 256) {
+    const int i = e / 64, kk = e - i * 64;
     const int64_t col = K0 + kk;
     if (col < ldt) {
-      const float x0 = (i < k && kk < nrow) ? tile[kk][i] : 0.0f;
-      const float x1 = (i < k && kk + 1 < nrow) ? tile[kk + 1][i] : 0.0f;
-      const uint16_t h0 = bf16_rne(x0), h1 = bf16_rne(x1);
-      const uint16_t l0 = bf16_rne(x0 - bf16_to_f32(h0)), l1 = bf16_rne(x1 - bf16_to_f32(h1));
-      *reinterpret_cast<uint32_t*>(Yth + i * ldt + col) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-      *reinterpret_cast<uint32_t*>(Ytl + i * ldt + col) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      const float x = tile[kk][i];
+      const uint16_t h = bf16_rne(x);
+      Yth[i * ldt + col] = h;
+      Ytl[i * ldt + col] = bf16_rne(x - bf16_to_f32(h));
     }
   }
 }
