@@ -136,8 +136,9 @@ uint64_t orc_pinned_set(int k, const double* G) {
 }
 
 /* Least squares restricted to the passive set F via the normal equations
- * G_FF x_F = f_F (the paper: "solving the least squares problem using normal
- * equations restricted to the passive set"), by Cholesky G_FF = L L^T built
+ * G_FF x_F = f_F (Section "Block Principal Pivoting" and Eq. KKT: on the
+ * passive set the gradient vanishes, so x_F solves the passive block of the
+ * normal equations), by Cholesky G_FF = L L^T built
  * row by row in index order.  An index whose pivot is <= 1e-12 * G_jj is
  * pinned and left out.  Writes x (x_i = 0 off F); returns the status bits. */
 static int solve_passive(int k, const double* G, const double* f, uint64_t* F, uint64_t* pinned,

@@ -77,6 +77,40 @@ def test_features_invariants():
     np.testing.assert_allclose(mlp.features(4.0 * G, 2.0 * R), phi, rtol=1e-12, atol=1e-15)
 
 
+def test_features_closed_form():
+    """Hand-worked feature vectors (Section "Block Principal Pivoting": the
+    network's input is the problem's right-hand side scaled by the square
+    roots of the Gram diagonal, then normalised, beside the diagonal over its
+    mean).  The Gram matrices are not diagonal and their diagonals are
+    distinct perfect squares, so s_i = f_i / sqrt(G_ii) is a small integer and
+    the unscaled f_i, f_i / G_ii and f_i * sqrt(G_ii) all give other
+    directions after the normalisation."""
+    G = np.array([[4.0, 2.0, 0.0], [2.0, 9.0, 3.0], [0.0, 3.0, 16.0]])
+    R = np.array([[2.0, -6.0, 8.0],     # s = (1, -2, 2), ||s|| = 3
+                  [0.0, 0.0, 0.0],      # zero right-hand side: s = 0
+                  [-4.0, 3.0, 0.0]])    # s = (-2, 1, 0), ||s|| = sqrt(5)
+    phi = mlp.features(G, R)
+    g = np.array([12.0, 27.0, 48.0]) / 29.0            # (4, 9, 16) / (29 / 3)
+    r5 = np.sqrt(5.0)
+    want = np.array([[1 / 3, -2 / 3, 2 / 3, *g],
+                     [0.0, 0.0, 0.0, *g],
+                     [-2 / r5, 1 / r5, 0.0, *g]])
+    np.testing.assert_allclose(phi, want, rtol=1e-15, atol=1e-16)
+    # the closed form tells the candidate scalings apart
+    for d_pow in (0.0, 1.0, -0.5):
+        alt = R[0] / np.diag(G) ** d_pow
+        alt = alt / np.linalg.norm(alt)
+        assert np.max(np.abs(alt - want[0, :3])) > 0.05, d_pow
+
+    # a pinned index (G_ii <= 1e-14 max G_ll) has s_i = 0; the diagonal part
+    # keeps its zero and the mean counts it
+    G2 = np.array([[25.0, 0.0, 5.0], [0.0, 0.0, 0.0], [5.0, 0.0, 1.0]])
+    R2 = np.array([[10.0, 7.0, -1.0]])                   # s = (2, 0, -1)
+    phi2 = mlp.features(G2, R2)
+    want2 = np.array([[2 / r5, 0.0, -1 / r5, 75 / 26, 0.0, 3 / 26]])
+    np.testing.assert_allclose(phi2, want2, rtol=1e-15, atol=1e-16)
+
+
 def test_targets_and_predict_roundtrip():
     k = 6
     masks = np.array([0, 1, 0b101101, 63], dtype=np.uint64)
