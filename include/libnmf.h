@@ -10,7 +10,9 @@
  *
  * Conventions for every entry point:
  *  - Pointers named as device pointers are device memory, owned and allocated
- *    by the caller; the library never allocates or frees device memory.
+ *    by the caller; the library never allocates or frees device memory (its
+ *    one static device array, the scratch of nmf_gram_noalloc, is part of the
+ *    loaded code object).
  *  - Matrices are row-major with an explicit leading dimension (in elements).
  *    H is always passed transposed, as Ht (n x k), so that both factor
  *    updates are "one problem per row of an (rows x k) matrix".
@@ -88,6 +90,23 @@ const char* nmf_version(void);
 int nmf_gram_workspace_bytes(int64_t rows, int k, size_t* bytes);
 int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* ws, size_t ws_bytes,
              void* stream);
+
+/* The same Gram matrix, for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument, and no allocation of any kind.  The block partials
+ * go to a static device array of NMF_GRAM_NOALLOC_SCRATCH_BYTES (32 MiB),
+ * which every device the library runs this on keeps until the process ends;
+ * it holds the partials of every valid (rows, k), and a request beyond it
+ * would return NMF_EINVAL.  Same kernels and summation order as nmf_gram, so
+ * the result is bit-identical to it.  The first call on a device looks up the
+ * array's address there (a runtime symbol query, no allocation).  All calls on
+ * one device share the array: calls that overlap in time on one device (two
+ * streams, two host threads) race and give wrong results; serialise them.
+ * Nothing in the array needs to start at zero, so what an earlier call left
+ * there is never read.  Errors: NMF_EINVAL as nmf_gram, NMF_EHIP if the
+ * address lookup fails, NMF_EUNSUPPORTED for a device index >= 64. */
+#define NMF_GRAM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int nmf_gram_noalloc(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* stream);
 
 /* ---- dense right-hand sides -----------------------------------------------
  * side NMF_SIDE_W: R (m x k) = A (m x n) * Y with Y = Ht (n x k), i.e. A H^T.

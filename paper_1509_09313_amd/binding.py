@@ -99,6 +99,7 @@ def lib():
             "nmf_version": ([], ctypes.c_char_p),
             "nmf_gram_workspace_bytes": ([i64, ci, sz], ci),
             "nmf_gram": ([i64, ci, vp, i64, vp, vp, ctypes.c_size_t, vp], ci),
+            "nmf_gram_noalloc": ([i64, ci, vp, i64, vp, vp], ci),
             "nmf_rhs_dense_workspace_bytes": ([ci, i64, i64, ci, ci, sz], ci),
             "nmf_rhs_dense_chain": ([ci, i64, i64, ci, ci, ctypes.POINTER(i64)], ci),
             "nmf_rhs_dense": ([ci, i64, i64, ci, vp, i64, vp, vp, i64, vp, i64, ci, vp, ctypes.c_size_t, vp], ci),
@@ -187,6 +188,18 @@ def nmf_gram(X, G=None):
     _check(lib().nmf_gram_workspace_bytes(rows, k, ctypes.byref(nb)))
     ws = _ws(nb.value)
     _check(lib().nmf_gram(rows, k, _ptr(X), _ld(X), _ptr(G), _ptr(ws), nb.value, _stream()))
+    return G
+
+
+def nmf_gram_noalloc(X, G):
+    """G = X^T X into the caller's G (k x k, float64), with no workspace and no
+    allocation (the library's static device scratch)."""
+    _dev(X, torch.float32, "X")
+    _dev(G, torch.float64, "G")
+    rows, k = X.shape
+    if tuple(G.shape) != (k, k) or not G.is_contiguous():
+        raise ValueError("G must be a contiguous k x k tensor")
+    _check(lib().nmf_gram_noalloc(rows, k, _ptr(X), _ld(X), _ptr(G), _stream()))
     return G
 
 

@@ -6,6 +6,8 @@
 // thread accumulates a 4 x 4 block of the upper triangle of G for one slice of
 // the tile's rows; slices and then blocks are combined in a fixed order, so
 // the FP64 result does not depend on scheduling.
+#include <mutex>
+
 #include "batched.h"
 #include "nmf_common.h"
 
@@ -228,5 +230,61 @@ extern "C" int nmf_gram(int64_t rows, int k, const float* X, int64_t ldx, double
   int nb;
   nmf::gram_plan(rows, k, c, &partial, &nb);
   if (!c.fits() || !ws) return nmf::fail(NMF_EWORKSPACE, "nmf_gram: workspace %zu < %zu bytes", ws_bytes, c.off);
+  return nmf::gram_launch(rows, k, X, ldx, G, partial, nb, nmf::as_stream(stream));
+}
+
+// ---- the variant without a workspace ------------------------------------------
+// The block partials of nmf_gram_noalloc live in this file-scope device array
+// instead of a caller workspace: kMaxBlocks partials of a 64 x 64 matrix
+// (32 MiB), enough for every valid (rows, k).  Each device holds its own copy
+// for the life of the process.  In host code `scratch` only names the array:
+// its device address comes from hipGetSymbolAddress, taken once per device.
+static __device__ __align__(256) double scratch[NMF_GRAM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+static_assert(NMF_GRAM_NOALLOC_SCRATCH_BYTES == (size_t)kMaxBlocks * 64 * 64 * sizeof(double),
+              "the scratch holds kMaxBlocks partials at k = 64");
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on its first use).
+int scratch_address(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return nmf::fail(NMF_EHIP, "nmf_gram_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return nmf::fail(NMF_EUNSUPPORTED, "nmf_gram_noalloc: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nmf::fail(NMF_EHIP, "nmf_gram_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return NMF_OK;
+}
+
+}  // namespace
+
+extern "C" int nmf_gram_noalloc(int64_t rows, int k, const float* X, int64_t ldx, double* G, void* stream) {
+  if (!nmf::valid_k(k)) return nmf::fail(NMF_EINVAL, "nmf_gram_noalloc: k=%d outside [1,64]", k);
+  if (rows < 0 || (rows > 0 && ldx < k))
+    return nmf::fail(NMF_EINVAL, "nmf_gram_noalloc: rows=%lld ldx=%lld", (long long)rows, (long long)ldx);
+  if (!G || (rows > 0 && !X)) return nmf::fail(NMF_EINVAL, "nmf_gram_noalloc: null pointer");
+  const int nb = gram_blocks(rows);
+  const size_t need = (size_t)nb * k * k * sizeof(double);
+  if (need > NMF_GRAM_NOALLOC_SCRATCH_BYTES)
+    return nmf::fail(NMF_EINVAL, "nmf_gram_noalloc: %zu bytes of partials exceed the %zu-byte scratch", need,
+                     (size_t)NMF_GRAM_NOALLOC_SCRATCH_BYTES);
+  double* partial = nullptr;
+  NMF_TRY(scratch_address(&partial));
+  // every partial slot the reduction reads is written by the partial kernel
+  // first, so nothing left by an earlier call is read
   return nmf::gram_launch(rows, k, X, ldx, G, partial, nb, nmf::as_stream(stream));
 }

@@ -52,6 +52,10 @@ def test_host_validation_without_gpu(L):
     nb = ctypes.c_size_t(0)
     assert lib.nmf_gram_workspace_bytes(1000, 8, ctypes.byref(nb)) == L.NMF_OK and nb.value > 0
     assert lib.nmf_gram(1000, 8, G, 8, G, G, nb.value - 1, None) == L.NMF_EWORKSPACE
+    # the variant without a workspace checks the same arguments first
+    assert lib.nmf_gram_noalloc(10, 0, G, 1, G, None) == L.NMF_EINVAL
+    assert lib.nmf_gram_noalloc(10, 8, G, 4, G, None) == L.NMF_EINVAL
+    assert lib.nmf_gram_noalloc(10, 8, G, 8, None, None) == L.NMF_EINVAL
     # BPP: bad caps and sizes
     assert lib.nnls_bpp_batched(8, 10, G, G, 8, G, 8, None, None, None, None, 0, 8, None, None) == L.NMF_EINVAL
     assert lib.nnls_bpp_batched(8, 10, G, G, 4, G, 8, None, None, None, None, 10, 8, None, None) == L.NMF_EINVAL
