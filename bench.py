@@ -1,9 +1,10 @@
 #!/usr/bin/env python3
 """ANLS-BPP NMF benchmark on one MI355X.
 
-Workload: the video-like dense matrix, 1,000,000 x 2,400 (FP32, 9.6 GB, built
-in HBM by the seeded generator), rank k = 30, 50 ANLS-BPP iterations from the
-seeded U[0,1) initial factors.  One step is one such 50-iteration run:
+Headline workload: the video-like dense matrix, 1,000,000 x 2,400 (FP32,
+9.6 GB, built in HBM by the seeded generator), rank k = 30, 50 ANLS-BPP
+iterations from the seeded U[0,1) initial factors.  One step is one such
+50-iteration run:
 
   learned + BF16x3 form (the reported value): iterations 1-5 with cold BPP
     and BF16x3 right-hand sides while collecting (features, final passive
@@ -15,11 +16,21 @@ seeded U[0,1) initial factors.  One step is one such 50-iteration run:
 value = iterations / second of the learned + BF16x3 form (training included),
 with the inputs (A, its BF16 planes, the initial factors) resident in HBM.
 Both forms' final relative objective is checked against the FP64 oracle's
-trajectory (tests/golden/video_1e6x2400_k30_oracle.json) when available.
+trajectory (tests/golden/video_1e6x2400_k30_oracle.json), and their final
+supports against the oracle's on a row sample (passive-set agreement).
 
-Per-phase HIP events inside the timed region give the dominant kernel's
-average duration for the roofline; the FP64 CPU oracle is timed on a bounded
-row sample for the CPU baseline.  Prints one JSON line.
+The same JSON line also carries, each with its own fixed step count:
+  warm_starts   the BF16x3 form with cold, previous-iterate and full-set BPP
+                starts beside the learned one (what the network gains);
+  local_solvers Algorithm 1 with HALS and MU on the same matrix;
+  batched       the 256-instance workload (graph-captured, autotuned);
+  dense         the planted 172,800 x 115,200 matrix (k = 50, 30 iterations),
+                plain FP32 and BF16x3;
+  sparse        the 207,360 x 138,240 CSR matrix at density 1e-3 (k = 50,
+                30 iterations), cold and previous-iterate starts;
+each with a roofline object for its dominant kernel and a CPU baseline (the
+FP64 oracle as it stands, timed on a bounded sample on the host's cores and
+at one thread, with the CPU model).
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -38,10 +49,16 @@ METRIC = "ANLS-BPP iters/sec at matched rel. objective (learned+BF16 vs plain FP
 GOLDEN = os.path.join(ROOT, "tests", "golden", "video_1e6x2400_k30_oracle.json")
 LOCAL_GOLDEN = os.path.join(ROOT, "tests", "golden", "video_1e6x2400_k30_local_oracle.json")
 KSWEEP_GOLDEN = os.path.join(ROOT, "tests", "golden", "video_1e6x2400_ksweep_oracle.json")
+BATCH_GOLDEN = os.path.join(ROOT, "tests", "golden", "batched_256_oracle.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+PRODUCT_PHASES = ("rhs_w", "rhs_h")
+MAIN_PHASES = ("rhs_w", "rhs_h", "bpp_w", "bpp_h", "gram_w", "gram_h", "infer_w", "infer_h")
 
 
 def parse(argv=None):
@@ -58,24 +75,244 @@ def parse(argv=None):
     ap.add_argument("--train-batch", type=int, default=1024)
     ap.add_argument("--collect-stride", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="host seconds per CPU-baseline sample (all threads; the 1-thread sample is sized alike)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-warm-starts", action="store_true", help="skip the cold / previous / full-set start forms")
+    ap.add_argument("--sub-steps", type=int, default=3,
+                    help="timed steps of every secondary form (warm starts, dense, sparse)")
+    ap.add_argument("--sub-warmup", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched measurement")
     ap.add_argument("--no-local", action="store_true", help="skip the HALS / MU local-solver measurement")
+    ap.add_argument("--no-dense", action="store_true", help="skip the planted 172800 x 115200 workload")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the CSR 207360 x 138240 workload")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--pmc", action="store_true", help="copy calibration + product kernels only (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-bpp", action="store_true",
                     help="batched BPP from cold and exact start sets at a mid-run state (for rocprofv3 --pmc)")
     ap.add_argument("--dense", action="store_true",
-                    help="the dense planted workload at full size (172800 x 115200, k = 50, 30 iterations)")
+                    help="only the dense planted workload at full size (172800 x 115200, k = 50, 30 iterations)")
     ap.add_argument("--ksweep", action="store_true",
                     help="time per iteration and its MM / NLS / Gram split for k = 10..50 on the video workload")
     ap.add_argument("--ksweep-iters", type=int, default=10)
     ap.add_argument("--sparse", action="store_true",
-                    help="the CSR workload (207360 x 138240): alone, or with --pmc its SpMM kernels too")
+                    help="only the CSR workload (207360 x 138240): alone, or with --pmc its SpMM kernels too")
     return ap.parse_args(argv)
 
 
+# ------------------------------------------------------------------ helpers --
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def mean_phases(timers):
+    """{phase: mean ms per launch} over one or more PhaseTimers."""
+    import numpy as np
+    acc = {}
+    for tm in timers:
+        for p, v in tm.phase_ms().items():
+            acc.setdefault(p, []).extend(v)
+    return {p: float(np.mean(v)) if v else 0.0 for p, v in acc.items()}
+
+
+def bpp_flops(stats, k, key):
+    """Algorithmic FP64 flops of the passive-set solves (Cholesky count):
+    sum over solves of |F|^3/3 + 2|F|^2 + 2k|F| (solve, two triangular
+    sweeps, dual)."""
+    tot = 0.0
+    for s in stats:
+        c = s[key]
+        tot += c[4] / 3.0 + 2.0 * c[3] + 2.0 * k * c[2]
+    return tot
+
+
+# sources that define each phase's kernels; counter results are tied to them
+PHASE_SOURCES = {
+    "rhs_w": ("rhs_bf16.hip", "nmf_common.h"), "rhs_h": ("rhs_bf16.hip", "nmf_common.h"),
+    "rhs_w_f32": ("rhs_dense.hip", "nmf_common.h"), "rhs_h_f32": ("rhs_dense.hip", "nmf_common.h"),
+    "spmm": ("rhs_csr.hip", "nmf_common.h"),
+    "bpp_w": ("bpp.hip", "nmf_common.h"), "bpp_h": ("bpp.hip", "nmf_common.h"),
+    "gram_w": ("gram.hip", "nmf_common.h"), "gram_h": ("gram.hip", "nmf_common.h"),
+    "infer_w": ("mlp.hip", "nmf_common.h"), "infer_h": ("mlp.hip", "nmf_common.h"),
+}
+
+
+def source_digest(phase):
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1509_09313_amd", "csrc")
+    for f in PHASE_SOURCES[phase]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(key, phase_sources):
+    """HBM bytes per launch from the stored FETCH_SIZE / WRITE_SIZE counts, or
+    None when absent or taken on other kernel sources."""
+    try:
+        with open(TRAFFIC) as fh:
+            tr = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = tr.get(key)
+    if ent and ent.get("source_sha256") == source_digest(phase_sources):
+        return ent["bytes_per_launch"]
+    return None
+
+
+def roofline(phase_ms, launches, m, n, k, prec, kind, stats=None, workload=None, nnz=None):
+    """The roofline object of the dominant kernel of one form.
+
+    phase_ms: mean ms per launch of each phase; stats: that form's decoded
+    per-iteration statistics (for the BPP flop count).  Algorithmic work per
+    launch: dense products read A once (4 B per entry, FP32 or the two BF16
+    planes), read the other factor and write R; the FP32 products are priced
+    against the FP32 MFMA peak when their MFMA floor exceeds their HBM floor
+    (2 m n k flops, k unpadded); CSR products read the CSR arrays, the factor
+    once and write R; BPP is priced in FP64 flops of the passive-set solves;
+    Gram and inference read their input once.  `traffic` comes from the
+    stored counter runs under the key "<workload>.<phase>" (the phase alone for
+    the headline form)."""
+    dom = max((p for p in MAIN_PHASES if p in phase_ms), key=lambda p: phase_ms[p] * launches.get(p, 1))
+    t = phase_ms[dom] * 1e-3
+    out = {"kernel_phase": dom, "avg_ms": phase_ms[dom]}
+    if dom in PRODUCT_PHASES:
+        rows = m if dom == "rhs_w" else n
+        contracted = n if dom == "rhs_w" else m
+        if kind == "csr":
+            alg = 8.0 * nnz + 8.0 * (rows + 1) + 4.0 * contracted * k + 4.0 * rows * k
+            src = "spmm"
+        else:
+            alg = 4.0 * m * n + 4.0 * contracted * k + 4.0 * rows * k
+            src = dom if prec == "bf16x3" else dom + "_f32"
+        flops = 2.0 * m * n * k
+        if kind == "dense" and prec == "fp32" and flops / (FP32_MFMA_PEAK_TFLOPS * 1e12) > alg / (HBM_PEAK_GBS * 1e9):
+            ach = flops / t / 1e12
+            out.update(bound="mfma", achieved=ach, peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                       frac=ach / FP32_MFMA_PEAK_TFLOPS, algorithmic_flops_per_launch=flops)
+        else:
+            ach = alg / t / 1e9
+            out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                       algorithmic_bytes_per_launch=alg)
+    elif dom in ("bpp_w", "bpp_h"):
+        n_it = max(1, len(stats))
+        fl = bpp_flops(stats, k, dom) / n_it
+        ach = fl / t / 1e12
+        out.update(bound="alu", achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / FP64_PEAK_TFLOPS,
+                   algorithmic_flops_per_launch=fl)
+        src = dom
+    else:
+        rows = m if dom in ("gram_w", "infer_w") else n
+        alg = 4.0 * rows * k
+        ach = alg / t / 1e9
+        out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                   algorithmic_bytes_per_launch=alg)
+        src = dom
+    out["traffic"] = counter_traffic(dom if workload is None else f"{workload}.{dom}", src)
+    return out
+
+
+def products_mfma(phase_ms, m, n, k, prec):
+    """MFMA rate of the two dense products: algorithmic 2 m n k flops per
+    product over its time, and the flops the MFMA units execute (k padded to
+    whole 32-wide tiles; three BF16 products for BF16x3) as a fraction of that
+    dtype's dense peak."""
+    kp = 32 * ((k + 31) // 32)
+    out = {}
+    for p in PRODUCT_PHASES:
+        t = phase_ms[p] * 1e-3
+        alg = 2.0 * m * n * k / t / 1e12
+        if prec == "bf16x3":
+            exe = 3.0 * 2.0 * m * n * kp / t / 1e12
+            peak = BF16_MFMA_PEAK_TFLOPS
+        else:
+            exe = 2.0 * m * n * kp / t / 1e12
+            peak = FP32_MFMA_PEAK_TFLOPS
+        out[p] = {"ms": phase_ms[p], "algorithmic_TFLOPs": alg, "executed_TFLOPs": exe, "peak_TFLOPs": peak,
+                  "mfma_utilisation": exe / peak}
+    return out
+
+
+def passive_set_agreement(W, Ht, ref, k):
+    """Agreement of the final supports {i : x_i > 0} with the FP64 oracle's
+    (stored for every `sample_stride_w`-th row of W and every row of H^T):
+    the fraction of (row, index) pairs on which both put the index in the
+    same set.  Where the oracle's passive set and support differ (indices
+    that end at exactly 0), the support is what both sides compare."""
+    import numpy as np
+    if ref is None or "support_w" not in ref:
+        return None
+    sw = int(ref["sample_stride_w"])
+    bits = np.arange(k, dtype=np.uint64)
+    res = {}
+    for name, X, key, stride in (("w", W, "support_w", sw), ("h", Ht, "support_h", 1)):
+        got = (X[::stride] > 0).cpu().numpy()
+        want = np.array([int(h, 16) for h in ref[key]], dtype=np.uint64)
+        want = ((want[:, None] >> bits[None, :]) & np.uint64(1)).astype(bool)
+        assert got.shape == want.shape, (got.shape, want.shape)
+        res[name] = {"rows": int(got.shape[0]), "agreement": float(np.mean(got == want)),
+                     "rows_identical": float(np.mean(np.all(got == want, axis=1)))}
+    tot = res["w"]["rows"] + res["h"]["rows"]
+    res["all"] = (res["w"]["agreement"] * res["w"]["rows"] + res["h"]["agreement"] * res["h"]["rows"]) / tot
+    res["sample"] = f"every {sw}th row of W and every row of H^T, against the FP64 oracle's final supports"
+    return res
+
+
+def cpu_model():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": avail}
+
+
+def _oracle_run(threads, **kw):
+    """oracle.anls at `threads` OpenMP threads; (seconds, result)."""
+    import oracle
+    prev = oracle.max_threads()
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        res = oracle.anls(**kw)
+        return time.perf_counter() - t0, res
+    finally:
+        oracle.set_threads(prev)
+
+
+def _scaled(phases, iters, factors):
+    """Per-iteration seconds at full size: each phase's seconds times its
+    scale factor, over the iterations run."""
+    return sum(phases[p] * factors[p] for p in phases) / iters
+
+
+def _baseline(per_iter_all, threads, sample, per_iter_1, sample_1):
+    out = {"value": 1.0 / per_iter_all, "unit": "iters/s", "cores": threads, "kind": "oracle", "sample": sample,
+           "seconds_per_iter_full": per_iter_all,
+           "one_thread": {"value": 1.0 / per_iter_1, "unit": "iters/s", "cores": 1, "sample": sample_1,
+                          "seconds_per_iter_full": per_iter_1}}
+    out.update(cpu_model())
+    return out
+
+
+# ------------------------------------------------------- headline workload --
 class Bench:
     def __init__(self, a):
         import torch
@@ -129,7 +366,6 @@ class Bench:
 
     # ---------------------------------------------------------------- forms --
     def learned_step(self, timers=None):
-        t = self.torch
         self.W.copy_(self.W0)
         self.Ht.copy_(self.Ht0)
         if timers:
@@ -147,7 +383,6 @@ class Bench:
         if timers:
             timers[0].detach(self.run1.opts)
             timers[1].detach(self.run2.opts)
-        del t
 
     def plain_step(self, timer=None):
         self.W.copy_(self.W0)
@@ -162,129 +397,120 @@ class Bench:
         return float(self.L.nmf_objective(self.M, self.W, self.Ht)[0].item())
 
 
-def timed(fn, steps, warmup):
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        fn()
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0
-
-
-def bpp_flops(stats, k, key):
-    """Algorithmic FP64 flops of the passive-set solves (Cholesky count):
-    sum over solves of |F|^3/3 + 2|F|^2 + 2k|F| (solve, two triangular
-    sweeps, dual)."""
-    tot = 0.0
-    for s in stats:
-        c = s[key]
-        tot += c[4] / 3.0 + 2.0 * c[3] + 2.0 * k * c[2]
-    return tot
-
-
-def roofline(bench, timers_l, stats_l):
-    """Dominant kernel of the learned form over the timed region."""
-    a = bench.a
-    L = bench.L
-    per = {p: [] for p in L.PHASES}
-    for tm in timers_l:
-        ph = tm.phase_ms()
-        for p in L.PHASES:
-            per[p] += ph[p]
-    totals = {p: sum(v) for p, v in per.items()}
-    launches = {p: len(v) for p, v in per.items()}
-    dom = max(("rhs_w", "rhs_h", "bpp_w", "bpp_h", "gram_w", "gram_h", "infer_w", "infer_h"), key=lambda p: totals[p])
-    avg_ms = totals[dom] / max(1, launches[dom])
-    m, n, k = a.m, a.n, a.k
-    out = {"kernel_phase": dom, "avg_ms": avg_ms,
-           "phase_ms_per_iter": {p: totals[p] / max(1, launches[p]) for p in L.PHASES}}
-    if dom in ("rhs_w", "rhs_h"):
-        rows = m if dom == "rhs_w" else n
-        contracted = n if dom == "rhs_w" else m
-        alg_bytes = 4.0 * m * n + 4.0 * contracted * k + 4.0 * rows * k
-        ach = alg_bytes / (avg_ms * 1e-3) / 1e9
-        out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                   algorithmic_bytes_per_launch=alg_bytes)
-    elif dom in ("bpp_w", "bpp_h"):
-        key = "bpp_w" if dom == "bpp_w" else "bpp_h"
-        # counters of the last timed step (every step repeats the same run)
-        n_it = sum(len(s) for s in stats_l)
-        fl = sum(bpp_flops(s, k, key) for s in stats_l) / max(1, n_it)
-        ach = fl / (avg_ms * 1e-3) / 1e12
-        out.update(bound="alu", achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / FP64_PEAK_TFLOPS,
-                   algorithmic_flops_per_launch=fl)
-    else:
-        rows = m if dom in ("gram_w", "infer_w") else n
-        alg_bytes = 4.0 * rows * k
-        ach = alg_bytes / (avg_ms * 1e-3) / 1e9
-        out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                   algorithmic_bytes_per_launch=alg_bytes)
-    out["traffic"] = None
+def load_golden():
     try:
-        with open(TRAFFIC) as fh:
-            tr = json.load(fh)
-        ent = tr.get(dom)
-        if ent and ent.get("source_sha256") == source_digest(dom):
-            out["traffic"] = ent["bytes_per_launch"]
+        with open(GOLDEN) as fh:
+            return json.load(fh)
     except (OSError, ValueError):
-        pass
+        return None
+
+
+def warm_start_forms(b, ref, learned_phases, learned_stats):
+    """What the trained networks gain: the BF16x3 form of the same 50
+    iterations with the trivial BPP starts (empty set, previous iteration's
+    set, full set) beside the learned one.  Per form: iterations/s of the
+    whole step, and over iterations cold_iters+1 .. iters (where the learned
+    form uses its networks) the W-side BPP time, the inference time, the
+    passive-set solves and KKT rounds per row, and fallbacks."""
+    import numpy as np
+    a, L = b.a, b.L
+    T0 = a.cold_iters
+
+    def summary(phases_per_iter, stats):
+        st = stats[T0:]
+        bw = float(np.mean(phases_per_iter["bpp_w"][T0:]))
+        iw = float(np.mean(phases_per_iter["infer_w"][T0:]))
+        bh = float(np.mean(phases_per_iter["bpp_h"][T0:]))
+        ih = float(np.mean(phases_per_iter["infer_h"][T0:]))
+        return {"bpp_w_ms": bw, "infer_w_ms": iw, "bpp_w_plus_infer_ms": bw + iw, "bpp_h_plus_infer_ms": bh + ih,
+                "solves_w_per_row": float(np.mean([s["bpp_w"][1] for s in st]) / a.m),
+                "rounds_w_per_row": float(np.mean([s["bpp_w"][0] for s in st]) / a.m),
+                "solves_h_per_col": float(np.mean([s["bpp_h"][1] for s in st]) / a.n),
+                "fallbacks": int(sum(s["fallback"] for s in st))}
+
+    out = {"workload": f"the headline matrix and start, BF16x3 products; per-iteration figures over iterations "
+                       f"{T0 + 1}-{a.iters} (where the learned form starts from the networks' sets)",
+           "steps": a.sub_steps, "warmup": a.sub_warmup}
+    lrn = summary(learned_phases, learned_stats)
+    out["learned"] = lrn
+    out["learned"]["note"] = "the headline form (value); its iterations/s are the line's value"
+    for name, warm in (("cold", L.NMF_WARM_COLD), ("prev", L.NMF_WARM_PREV), ("full_set", L.NMF_WARM_ALL)):
+        run = L.Anls(b.M, a.k, L.make_opts(prec=L.NMF_BF16X3, warm=warm, trace=True, reset_masks=True))
+        stats = L.new_stats(a.iters)
+
+        def step(timer=None):
+            b.W.copy_(b.W0)
+            b.Ht.copy_(b.Ht0)
+            if timer:
+                timer.attach(run.opts)
+            run.run(b.W, b.Ht, a.iters, stats)
+            if timer:
+                timer.detach(run.opts)
+
+        t = timed(step, a.sub_steps, a.sub_warmup)
+        r = b.final_r()
+        agree = passive_set_agreement(b.W, b.Ht, ref, a.k)
+        tm = L.PhaseTimer(a.iters)
+        step(tm)
+        b.torch.cuda.synchronize()
+        ph = tm.phase_ms()
+        tm.close()
+        o = summary(ph, L.decode_stats(stats))
+        o.update(iters_per_s=a.iters * a.sub_steps / t, final_r=r,
+                 abs_dr_vs_oracle=None if ref is None else abs(r - ref["r_full"][-1]),
+                 passive_set_agreement=None if agree is None else agree["all"])
+        out[name] = o
+        print(f"# bf16x3 {name} starts: {1e3 * t / a.sub_steps:.1f} ms/step, W BPP {o['bpp_w_ms']:.3f} ms, "
+              f"{o['solves_w_per_row']:.3f} solves/row", file=sys.stderr, flush=True)
+        del run
+    best = min(("cold", "prev", "full_set"), key=lambda nm: out[nm]["bpp_w_plus_infer_ms"])
+    out["best_trivial_start"] = best
+    out["learned_minus_best_trivial_ms"] = lrn["bpp_w_plus_infer_ms"] - out[best]["bpp_w_plus_infer_ms"]
+    out["learned_beats_every_trivial_start"] = out["learned_minus_best_trivial_ms"] < 0.0
     return out
 
 
-# sources that define each phase's kernels; counter results are tied to them
-PHASE_SOURCES = {
-    "rhs_w": ("rhs_bf16.hip", "nmf_common.h"), "rhs_h": ("rhs_bf16.hip", "nmf_common.h"),
-    "bpp_w": ("bpp.hip", "nmf_common.h"), "bpp_h": ("bpp.hip", "nmf_common.h"),
-    "gram_w": ("gram.hip", "nmf_common.h"), "gram_h": ("gram.hip", "nmf_common.h"),
-    "infer_w": ("mlp.hip", "nmf_common.h"), "infer_h": ("mlp.hip", "nmf_common.h"),
-}
-
-
-def source_digest(phase):
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1509_09313_amd", "csrc")
-    for f in PHASE_SOURCES[phase]:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def cpu_baseline(bench, seconds):
-    """The FP64 oracle (as it stands) on a bounded sample of the workload: the
-    first S rows for I ANLS-BPP iterations, about `seconds` of host work;
-    the time per iteration is scaled by m / S to the full matrix."""
-    import numpy as np
-
+def cpu_baseline_video(b, seconds):
+    """The FP64 oracle (as it stands) on a bounded sample of the headline
+    workload: the first S rows for I ANLS-BPP iterations.  Per-iteration
+    seconds at full size: the oracle's phases that run over the rows of W
+    (both products, the W-side BPP, the Gram products and the objective sums)
+    scaled by m / S, the H-side BPP (n problems whatever S is) as timed."""
     import oracle
-    a = bench.a
-    W0 = bench.W0.cpu().numpy()
-    H0 = bench.Ht0.cpu().numpy()
+    a = b.a
+    W0 = b.W0.cpu().numpy()
+    H0 = b.Ht0.cpu().numpy()
+    nthr = oracle.max_threads()
 
-    def run(S, iters):
-        A = bench.A[:S].cpu().numpy()
-        t0 = time.perf_counter()
-        oracle.anls(a.k, W0[:S], H0, iters, dense=A)
-        return time.perf_counter() - t0
+    def run(S, iters, threads):
+        A = b.A[:S].cpu().numpy()
+        t, res = _oracle_run(threads, k=a.k, W0=W0[:S], Ht0=H0, T=iters, dense=A)
+        ph = res["phase_seconds"]
+        f = {p: a.m / S for p in ph}
+        f["bpp_h"] = 1.0
+        return t, _scaled(ph, iters, f)
 
-    S, I = min(a.m, 20_000), 1
-    t = run(S, I)
-    S2 = int(min(a.m, max(S, S * seconds / max(t, 1e-3))))
-    if S2 > S:
-        S, t = S2, run(S2, I)
-    if t < 0.5 * seconds:
-        I = int(min(a.iters, max(1, seconds // max(t, 1e-3))))
-        if I > 1:
-            t = run(S, I)
-    per_iter = t / I * a.m / S
-    return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{I} ANLS-BPP iteration(s) of the FP64 oracle on rows 0..{S - 1} ({S} x {a.n}, k={a.k}) "
-                      f"from the benchmark's initial factors, {t:.2f} s, per iteration scaled by {a.m}/{S} to the "
-                      f"full matrix",
-            "seconds_per_iter_full": per_iter}
+    def sized(threads, budget):
+        S, I = min(a.m, 20_000), 1
+        t, per = run(S, I, threads)
+        S2 = int(min(a.m, max(S, S * budget / max(t, 1e-3))))
+        if S2 > S:
+            S, (t, per) = S2, run(S2, I, threads)
+        if t < 0.5 * budget and S == a.m:
+            I = int(min(a.iters, max(1, budget // max(t, 1e-3))))
+            if I > 1:
+                t, per = run(S, I, threads)
+        return S, I, t, per
+
+    S, I, t, per = sized(nthr, seconds)
+    S1, I1, t1, per1 = sized(1, seconds)
+
+    def desc(S, I, t, thr):
+        return (f"{I} ANLS-BPP iteration(s) of the FP64 oracle on rows 0..{S - 1} ({S} x {a.n}, k={a.k}) from the "
+                f"benchmark's initial factors, {t:.2f} s on {thr} thread(s); row-side phases scaled by {a.m}/{S}, "
+                f"the H-side BPP as timed")
+
+    return _baseline(per, nthr, desc(S, I, t, nthr), per1, desc(S1, I1, t1, 1))
 
 
 def local_forms(bench):
@@ -299,7 +525,7 @@ def local_forms(bench):
     if os.path.exists(LOCAL_GOLDEN) and (a.m, a.n, a.k, a.iters) == (1_000_000, 2_400, 30, 50):
         with open(LOCAL_GOLDEN) as fh:
             ref = json.load(fh)
-    out = {}
+    out = {"steps": a.sub_steps, "warmup": a.sub_warmup}
     for name, solver in (("hals", L.NMF_SOLVER_HALS), ("mu", L.NMF_SOLVER_MU)):
         run = L.Anls(bench.M, a.k, L.make_opts(prec=L.NMF_BF16X3, trace=True, solver=solver))
         stats = L.new_stats(a.iters)
@@ -313,7 +539,7 @@ def local_forms(bench):
             if timer:
                 timer.detach(run.opts)
 
-        t = timed(step, a.steps, a.warmup)
+        t = timed(step, a.sub_steps, a.sub_warmup)
         r = bench.final_r()
         tm = L.PhaseTimer(a.iters)
         step(tm)
@@ -321,19 +547,15 @@ def local_forms(bench):
         ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
         tm.close()
         o = None if ref is None else ref[name]["r_full"][-1]
-        # the FP64 oracle's own time for the same 50 iterations, recorded when the stored run was
-        # written (8 host threads of the machine that wrote it, not this one)
-        o_s = None if ref is None else ref[name]["oracle_seconds"] / a.iters
         # the W-side update streams R (read) and W (read and written): 12 k bytes per row
         alg = 12.0 * a.k * a.m
         gbs = alg / (ph["bpp_w"] * 1e-3) / 1e9
-        out[name] = {"iters_per_s": a.iters * a.steps / t, "ms_per_step": t / a.steps * 1e3, "final_r": r,
-                     "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o),
+        out[name] = {"iters_per_s": a.iters * a.sub_steps / t, "ms_per_step": t / a.sub_steps * 1e3,
+                     "final_r": r, "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o),
                      "update_ms_per_iter": {"w": ph["bpp_w"], "h": ph["bpp_h"]},
-                     "update_w_roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
-                                           "frac": gbs / 8000.0, "algorithmic_bytes_per_launch": alg,
+                     "update_w_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                           "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg,
                                            "fp64_tflops": 2.0 * a.k * a.k * a.m / (ph["bpp_w"] * 1e-3) / 1e12},
-                     "oracle_s_per_iter_recorded": o_s,
                      "phase_ms_per_iter": ph}
         print(f"# {name}: {out[name]['ms_per_step']:.1f} ms/step, final r {r:.8f}", file=sys.stderr, flush=True)
     out["note"] = ("the update phase is reported in the bpp_* slots of phase_ms_per_iter; "
@@ -341,11 +563,7 @@ def local_forms(bench):
     return out
 
 
-KS = (10, 20, 30, 40, 50)
-
-BATCH_GOLDEN = os.path.join(ROOT, "tests", "golden", "batched_256_oracle.json")
-
-
+# ------------------------------------------------------------ batched (c4) --
 def batched(a):
     """The 256-instance batched workload: autotuned work items, 30 iterations
     captured as one graph, each launch from the same initial factors (cold
@@ -397,26 +615,237 @@ def batched(a):
     alg = float(sum(8.0 * m * n + 16.0 * k * (m + n) for m, n, k in shapes))
     ach = alg / (ms_run / T * 1e-3) / 1e9
     b.close()
-    return {"workload": "256 planted dense instances, m log-uniform [500,8000], n log-uniform [500,4000], "
-                        "k in {10,20,50}, BF16x3 products, FP64 Gram/BPP, 30 iterations per graph launch",
-            "iters_per_s": T / (ms_run * 1e-3), "ms_per_30_iterations": ms_run, "tune": best.as_dict(),
-            "tuner_ms_per_iteration_from_cold": tuned_ms,
-            "max_abs_dr_vs_oracle": None if errs is None else float(max(errs)),
-            "mean_abs_dr_vs_oracle": None if errs is None else float(np.mean(errs)),
-            "algorithmic_bytes_per_iteration": alg, "achieved_GBps": ach, "hbm_frac": ach / HBM_PEAK_GBS}
+    out = {"workload": "256 planted dense instances, m log-uniform [500,8000], n log-uniform [500,4000], "
+                       "k in {10,20,50}, BF16x3 products, FP64 Gram/BPP, 30 iterations per graph launch",
+           "iters_per_s": T / (ms_run * 1e-3), "ms_per_30_iterations": ms_run, "tune": best.as_dict(),
+           "tuner_ms_per_iteration_from_cold": tuned_ms,
+           "max_abs_dr_vs_oracle": None if errs is None else float(max(errs)),
+           "mean_abs_dr_vs_oracle": None if errs is None else float(np.mean(errs)),
+           "abs_dr_vs_oracle_quantiles": None if errs is None else
+           {q: float(np.quantile(errs, float(q))) for q in ("0.5", "0.9", "0.99")},
+           "algorithmic_bytes_per_iteration": alg, "achieved_GBps": ach, "hbm_frac": ach / HBM_PEAK_GBS}
+    del probs, b
+    return out
 
 
-def sparse_inputs(torch):
+# -------------------------------------------------------------- dense (c2) --
+def _form_run(L, M, k, W, Ht, W0, Ht0, T, steps, warmup, **kw):
+    """Times `steps` runs of T iterations of one form from (W0, Ht0), then one
+    more with per-phase events; (seconds, phase ms per launch, decoded stats)."""
+    import torch
+    run = L.Anls(M, k, L.make_opts(trace=True, reset_masks=True, **kw))
+    stats = L.new_stats(T)
+
+    def step(timer=None):
+        W.copy_(W0)
+        Ht.copy_(Ht0)
+        if timer:
+            timer.attach(run.opts)
+        run.run(W, Ht, T, stats)
+        if timer:
+            timer.detach(run.opts)
+
+    t = timed(step, steps, warmup)
+    tm = L.PhaseTimer(T)
+    step(tm)
+    torch.cuda.synchronize()
+    ph = mean_phases([tm])
+    tm.close()
+    return t, ph, L.decode_stats(stats)
+
+
+def dense_workload(a, steps, warmup, with_cpu=True):
+    """The planted workload at full size (172,800 x 115,200, rank-50 U[0,1)
+    factors plus 0.01 U[0,1) noise; A is 79.6 GB in FP32), k = 50, 30
+    cold-BPP iterations per step: plain FP32 products, then BF16x3 products
+    from the padded planes of A and A^T (159 GB more, made after the FP32
+    form).  Per form: iterations/s, the phase split, the products' rate and
+    MFMA utilisation, the roofline of the dominant kernel and the final
+    relative objective (the two must agree within 1e-5; the FP64 oracle
+    cannot run this size, the sampled full-size tests check it instead)."""
+    import torch
+
+    from nmf_inputs import configs as C
+    from nmf_inputs import device as gen
+    from paper_1509_09313_amd import binding as L
+    seed, m, n, k, T = C.seed_for(2), 172_800, 115_200, 50, 30
+    t0 = time.perf_counter()
+    A = gen.planted(seed, m, n, k)
+    W0, Ht0 = gen.init_factors(seed, m, n, k)
+    M = L.Matrix(dense=A)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    print(f"# dense inputs: {t_gen:.1f}s", file=sys.stderr, flush=True)
+    W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
+    prod_bytes = 2.0 * (4.0 * m * n + 4.0 * n * k + 4.0 * m * k)
+
+    def form(prec, name):
+        t, ph, st = _form_run(L, M, k, W, Ht, W0, Ht0, T, steps, warmup, prec=prec)
+        r = float(L.nmf_objective(M, W, Ht)[0])
+        mm = (ph["rhs_w"] + ph["rhs_h"]) * 1e-3
+        out = {"iters_per_s": T * steps / t, "ms_per_iter": t / (steps * T) * 1e3, "final_r": r,
+               "phase_ms_per_iter": ph, "products_GBps": prod_bytes / mm / 1e9,
+               "products_hbm_frac": prod_bytes / mm / 8e12,
+               "products_mfma": products_mfma(ph, m, n, k, name),
+               "roofline": roofline(ph, {}, m, n, k, name, "dense", st, workload=f"dense_{name}"),
+               "capped": int(sum(s["capped"] for s in st))}
+        print(f"# dense {name}: {out['ms_per_iter']:.2f} ms/iter, products {out['products_GBps']:.0f} GB/s, "
+              f"r {r:.8f}", file=sys.stderr, flush=True)
+        return out
+
+    res = {"workload": f"planted dense {m}x{n} (rank 50 U[0,1) factors + 0.01 U[0,1) noise), k={k}, {T} cold-BPP "
+                       f"iterations per step from the seeded start; stands in for the paper's DSYN",
+           "steps": steps, "warmup": warmup, "generate_s": t_gen}
+    res["fp32"] = form(L.NMF_F32, "fp32")
+    t0 = time.perf_counter()
+    M.add_split()
+    torch.cuda.synchronize()
+    res["one_time_split_s"] = time.perf_counter() - t0
+    res["bf16x3"] = form(L.NMF_BF16X3, "bf16x3")
+    res["abs_dr_bf16x3_vs_fp32"] = abs(res["bf16x3"]["final_r"] - res["fp32"]["final_r"])
+    res["speedup_bf16x3_vs_fp32"] = res["bf16x3"]["iters_per_s"] / res["fp32"]["iters_per_s"]
+    del M, A, W, Ht, W0, Ht0
+    torch.cuda.empty_cache()
+    if with_cpu:
+        res["cpu_baseline"] = cpu_baseline_dense(a.cpu_seconds)
+    return res
+
+
+def cpu_baseline_dense(seconds):
+    """The FP64 oracle on the 1,728 x 1,152 instance of the same generator (the
+    top-left block of the full matrix), k = 50, scaled to 172,800 x 115,200:
+    the two products by the area ratio, the BPP of each side by its problem
+    count ratio, the Gram products and objective sums by (m + n)."""
+    import oracle
+    from nmf_inputs import configs as C
+    w = C.WORKLOADS["c2s"]
+    A = C.dense_rows(w, range(w.m))
+    W0, H0 = C.init_w(w.seed, w.m, w.k), C.init_ht(w.seed, w.n, w.k)
+    M, N = 172_800, 115_200
+    f = {"rhs_w": M * N / (w.m * w.n), "rhs_h": M * N / (w.m * w.n), "bpp_w": M / w.m, "bpp_h": N / w.n,
+         "gram": (M + N) / (w.m + w.n), "objective": (M + N) / (w.m + w.n)}
+    nthr = oracle.max_threads()
+
+    def sized(threads):
+        t, res = _oracle_run(threads, k=w.k, W0=W0, Ht0=H0, T=1, dense=A)
+        I = int(min(w.iters, max(1, seconds // max(t, 1e-3))))
+        if I > 1:
+            t, res = _oracle_run(threads, k=w.k, W0=W0, Ht0=H0, T=I, dense=A)
+        return I, t, _scaled(res["phase_seconds"], I, f)
+
+    I, t, per = sized(nthr)
+    I1, t1, per1 = sized(1)
+
+    def desc(I, t, thr):
+        return (f"{I} ANLS-BPP iteration(s) of the FP64 oracle on the {w.m} x {w.n} instance (k={w.k}, the top-left "
+                f"block of the same generator), {t:.2f} s on {thr} thread(s); products scaled by the area ratio "
+                f"{f['rhs_w']:.0f}, each side's BPP by its problem-count ratio (100), Gram and objective by (m+n)")
+
+    return _baseline(per, nthr, desc(I, t, nthr), per1, desc(I1, t1, 1))
+
+
+# ------------------------------------------------------------- sparse (c3) --
+def sparse_inputs(torch, workers=8):
     """The CSR workload (207,360 x 138,240, density 1e-3) built on the host
-    from its seeded recipe and uploaded: CSR(A) and CSR(A^T)."""
+    from its seeded recipe and uploaded: CSR(A) and CSR(A^T); returns the
+    host arrays too."""
     from nmf_inputs import configs as C
     seed, m, n = C.seed_for(3), 207_360, 138_240
-    rp, ci, va = C.sparse_csr(seed, m, n, 1e-3)
+    rp, ci, va = C.sparse_csr(seed, m, n, 1e-3, workers=workers)
     rpt, cit, vat = C.csr_transpose(m, n, rp, ci, va)
-    d = [torch.from_numpy(x).cuda() for x in (rp, ci, va, rpt, cit, vat)]
-    return seed, m, n, d
+    host = (rp, ci, va, rpt, cit, vat)
+    d = [torch.from_numpy(x).cuda() for x in host]
+    return seed, m, n, d, host
 
 
+def sparse_workload(a, steps, warmup, with_cpu=True):
+    """The CSR workload at full size: plain FP32 SpMM right-hand sides, FP64
+    Gram and BPP, 30 iterations per step from the seeded start, cold BPP and
+    the previous iteration's passive sets; the SpMM rate on algorithmic bytes
+    and the roofline of the dominant kernel."""
+    import torch
+
+    from nmf_inputs import device as gen
+    from paper_1509_09313_amd import binding as L
+    t0 = time.perf_counter()
+    seed, m, n, d, host = sparse_inputs(torch)
+    k, T = 50, 30
+    W0, Ht0 = gen.init_factors(seed, m, n, k)
+    M = L.Matrix(csr=(d[0], d[1], d[2]), csr_t=(d[3], d[4], d[5]), shape=(m, n))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    print(f"# sparse inputs: {t_gen:.1f}s (host generation)", file=sys.stderr, flush=True)
+    W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
+    nnz = int(d[2].numel())
+    # algorithmic bytes of one SpMM: int32 column + FP32 value per nonzero, the
+    # row pointers, Y read once, R written once
+    alg_w = 8.0 * nnz + 8.0 * (m + 1) + 4.0 * n * k + 4.0 * m * k
+    alg_h = 8.0 * nnz + 8.0 * (n + 1) + 4.0 * m * k + 4.0 * n * k
+
+    def form(warm):
+        import numpy as np
+        t, ph, st = _form_run(L, M, k, W, Ht, W0, Ht0, T, steps, warmup, prec=L.NMF_F32, warm=warm)
+        r = float(L.nmf_objective(M, W, Ht)[0])
+        return {"iters_per_s": T * steps / t, "ms_per_step": t / steps * 1e3, "final_r": r,
+                "phase_ms_per_iter": ph,
+                "spmm_w_GBps": alg_w / (ph["rhs_w"] * 1e-3) / 1e9, "spmm_h_GBps": alg_h / (ph["rhs_h"] * 1e-3) / 1e9,
+                "spmm_w_hbm_frac": alg_w / (ph["rhs_w"] * 1e-3) / 8e12,
+                "bpp_rounds_per_problem": float(np.mean([(s["bpp_w"][0] + s["bpp_h"][0]) / (m + n) for s in st])),
+                "roofline": roofline(ph, {}, m, n, k, "fp32", "csr", st, workload="sparse", nnz=nnz),
+                "capped": int(sum(s["capped"] for s in st))}
+
+    res = {"workload": f"CSR {m}x{n}, density 1e-3 ({nnz} nonzeros), k={k}, {T} iterations per step, "
+                       f"FP32 SpMM, FP64 Gram/BPP, cold BPP; stands in for the paper's SSYN",
+           "steps": steps, "warmup": warmup, "generate_s": t_gen}
+    res.update(form(L.NMF_WARM_COLD))
+    print(f"# sparse cold: {res['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    res["warm_prev"] = form(L.NMF_WARM_PREV)
+    res["warm_prev"]["abs_dr_vs_cold"] = abs(res["warm_prev"]["final_r"] - res["final_r"])
+    print(f"# sparse prev: {res['warm_prev']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    del M, d, W, Ht, W0, Ht0
+    torch.cuda.empty_cache()
+    if with_cpu:
+        res["cpu_baseline"] = cpu_baseline_sparse(a.cpu_seconds, host, m, n, k, seed)
+    return res
+
+
+def cpu_baseline_sparse(seconds, host, m, n, k, seed):
+    """The FP64 oracle on the full CSR matrix for one ANLS-BPP iteration from
+    the benchmark's start (all threads).  At one thread, the first S rows of A
+    (with CSR of that block's transpose) for one iteration: the SpMMs scaled by
+    the nonzero ratio, the W-side BPP by m / S, and the H-side BPP from the
+    W side's per-problem time times n (the block's columns hold only S/m of a
+    column's nonzeros, so its H-side problems are not representative)."""
+    import oracle
+    from nmf_inputs import configs as C
+    rp, ci, va, rpt, cit, vat = host
+    W0, H0 = C.init_w(seed, m, k), C.init_ht(seed, n, k)
+    nthr = oracle.max_threads()
+    t, res = _oracle_run(nthr, k=k, W0=W0, Ht0=H0, T=1, csr=(rp, ci, va), csr_t=(rpt, cit, vat), shape=(m, n))
+    I = int(min(30, max(1, seconds // max(t, 1e-3))))
+    if I > 1:
+        t, res = _oracle_run(nthr, k=k, W0=W0, Ht0=H0, T=I, csr=(rp, ci, va), csr_t=(rpt, cit, vat), shape=(m, n))
+    per = sum(res["phase_seconds"].values()) / I
+    desc = (f"{I} ANLS-BPP iteration(s) of the FP64 oracle on the full {m} x {n} CSR matrix (k={k}) from the "
+            f"benchmark's initial factors, {t:.2f} s on {nthr} thread(s)")
+    # one thread: a row block sized from the all-thread time per iteration
+    S = int(min(m, max(2000, m * seconds / max(per * nthr, 1e-3))))
+    nnz_s = int(rp[S])
+    rps, cis, vas = rp[:S + 1].copy(), ci[:nnz_s].copy(), va[:nnz_s].copy()
+    rpst, cist, vast = C.csr_transpose(S, n, rps, cis, vas)
+    t1, res1 = _oracle_run(1, k=k, W0=W0[:S], Ht0=H0, T=1, csr=(rps, cis, vas), csr_t=(rpst, cist, vast),
+                           shape=(S, n))
+    ph = res1["phase_seconds"]
+    nnz = int(rp[-1])
+    per1 = ((ph["rhs_w"] + ph["rhs_h"]) * nnz / max(nnz_s, 1) + ph["bpp_w"] * (m + n) / S
+            + (ph["gram"] + ph["objective"]) * (m + n) / (S + n))
+    desc1 = (f"1 ANLS-BPP iteration of the FP64 oracle on rows 0..{S - 1} of the CSR matrix ({nnz_s} nonzeros), "
+             f"{t1:.2f} s on 1 thread; SpMMs scaled by the nonzero ratio, BPP by (m+n)/S from the W side's "
+             f"per-problem time, Gram and objective by (m+n)/(S+n)")
+    return _baseline(per, nthr, desc, per1, desc1)
+
+
+# ------------------------------------------------------------- other modes --
 def pmc_mode(a):
     """Launches a plain copy of known size, then each product kernel a few
     times (BF16x3 and FP32 on the video-like matrix, both Gram passes, and
@@ -440,7 +869,7 @@ def pmc_mode(a):
         L.nmf_gram(b.W0)
         L.nmf_gram(b.Ht0)
     if a.sparse:
-        seed, m, n, d = sparse_inputs(torch)
+        seed, m, n, d, _ = sparse_inputs(torch)
         W0, Ht0 = b.gen.init_factors(seed, m, n, 50)
         for _ in range(3):
             L.nmf_rhs_csr(d[0], d[1], d[2], Ht0, m, n)
@@ -477,128 +906,7 @@ def pmc_bpp_mode(a):
     print(json.dumps({"pmc_bpp": "done", "problems": m, "k": k}))
 
 
-def dense_mode(a):
-    """The dense planted workload at full size (172,800 x 115,200, rank-50
-    U[0,1) factors plus 0.01 U[0,1) noise; A is 79.6 GB in FP32), k = 50, 30
-    cold-BPP iterations per step: plain FP32 products, then BF16x3 products
-    from the padded planes of A and A^T (159 GB more, made after the FP32
-    form).  Reports iterations/s, the phase split, the products' rate (HBM
-    bytes and FP32 MFMA flops) and the final relative objective of each form
-    (the two must agree within 1e-5; the FP64 oracle cannot run this size, the
-    sampled full-size tests check it instead)."""
-    import numpy as np
-    import torch
-
-    from nmf_inputs import configs as C
-    from nmf_inputs import device as gen
-    from paper_1509_09313_amd import binding as L
-    seed, m, n, k, T = C.seed_for(2), 172_800, 115_200, 50, 30
-    t0 = time.perf_counter()
-    A = gen.planted(seed, m, n, k)
-    W0, Ht0 = gen.init_factors(seed, m, n, k)
-    M = L.Matrix(dense=A)
-    torch.cuda.synchronize()
-    print(f"# dense inputs: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
-    prod_bytes = 2.0 * (4.0 * m * n + 4.0 * n * k + 4.0 * m * k)
-    prod_flops = 2.0 * 2.0 * m * n * k
-
-    def form(prec):
-        run = L.Anls(M, k, L.make_opts(prec=prec, trace=True, reset_masks=True))
-        stats = L.new_stats(T)
-
-        def step(timer=None):
-            W.copy_(W0)
-            Ht.copy_(Ht0)
-            if timer:
-                timer.attach(run.opts)
-            run.run(W, Ht, T, stats)
-            if timer:
-                timer.detach(run.opts)
-
-        t = timed(step, a.steps, a.warmup)
-        tm = L.PhaseTimer(T)
-        step(tm)
-        torch.cuda.synchronize()
-        ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
-        tm.close()
-        r = float(L.nmf_objective(M, W, Ht)[0])
-        mm = (ph["rhs_w"] + ph["rhs_h"]) * 1e-3
-        st = L.decode_stats(stats)
-        out = {"iters_per_s": T * a.steps / t, "ms_per_iter": t / (a.steps * T) * 1e3, "final_r": r,
-               "phase_ms_per_iter": ph, "products_GBps": prod_bytes / mm / 1e9,
-               "products_hbm_frac": prod_bytes / mm / 8e12,
-               "products_fp32_mfma_TFLOPs": prod_flops / mm / 1e12, "capped": int(sum(s["capped"] for s in st))}
-        print(f"# dense {'fp32' if prec == L.NMF_F32 else 'bf16x3'}: {out['ms_per_iter']:.2f} ms/iter, "
-              f"products {out['products_GBps']:.0f} GB/s, r {r:.8f}", file=sys.stderr, flush=True)
-        return out
-
-    res = {"workload": f"planted dense {m}x{n} (rank 50 U[0,1) factors + 0.01 U[0,1) noise), k={k}, {T} cold-BPP "
-                       f"iterations per step from the seeded start"}
-    res["fp32"] = form(L.NMF_F32)
-    M.add_split()
-    torch.cuda.synchronize()
-    res["bf16x3"] = form(L.NMF_BF16X3)
-    res["abs_dr_bf16x3_vs_fp32"] = abs(res["bf16x3"]["final_r"] - res["fp32"]["final_r"])
-    print(json.dumps({"dense": res}))
-
-
-def sparse_mode(a):
-    """The CSR workload at full size: plain FP32 SpMM right-hand sides, FP64
-    Gram and BPP, `iters` iterations per step from the seeded start (cold
-    BPP), with the SpMM rate on algorithmic bytes."""
-    import numpy as np
-    import torch
-
-    from nmf_inputs import device as gen
-    from paper_1509_09313_amd import binding as L
-    t0 = time.perf_counter()
-    seed, m, n, d = sparse_inputs(torch)
-    k, T = 50, 30
-    W0, Ht0 = gen.init_factors(seed, m, n, k)
-    M = L.Matrix(csr=(d[0], d[1], d[2]), csr_t=(d[3], d[4], d[5]), shape=(m, n))
-    torch.cuda.synchronize()
-    print(f"# sparse inputs: {time.perf_counter() - t0:.1f}s (host generation)", file=sys.stderr, flush=True)
-    W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
-    nnz = int(d[2].numel())
-    # algorithmic bytes of one SpMM: int32 column + FP32 value per nonzero, the
-    # row pointers, Y read once, R written once
-    alg_w = 8.0 * nnz + 8.0 * (m + 1) + 4.0 * n * k + 4.0 * m * k
-    alg_h = 8.0 * nnz + 8.0 * (n + 1) + 4.0 * m * k + 4.0 * n * k
-
-    def form(warm):
-        run = L.Anls(M, k, L.make_opts(prec=L.NMF_F32, warm=warm, trace=True, reset_masks=True))
-        stats = L.new_stats(T)
-
-        def step(timer=None):
-            W.copy_(W0)
-            Ht.copy_(Ht0)
-            if timer:
-                timer.attach(run.opts)
-            run.run(W, Ht, T, stats)
-            if timer:
-                timer.detach(run.opts)
-
-        t = timed(step, a.steps, a.warmup)
-        tm = L.PhaseTimer(T)
-        step(tm)
-        torch.cuda.synchronize()
-        ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
-        tm.close()
-        r = float(L.nmf_objective(M, W, Ht)[0])
-        st = L.decode_stats(stats)
-        return {"iters_per_s": T * a.steps / t, "ms_per_step": t / a.steps * 1e3, "final_r": r,
-                "phase_ms_per_iter": ph,
-                "spmm_w_GBps": alg_w / (ph["rhs_w"] * 1e-3) / 1e9, "spmm_h_GBps": alg_h / (ph["rhs_h"] * 1e-3) / 1e9,
-                "bpp_rounds_per_problem": float(np.mean([(s["bpp_w"][0] + s["bpp_h"][0]) / (m + n) for s in st])),
-                "capped": int(sum(s["capped"] for s in st))}
-
-    res = {"workload": f"CSR {m}x{n}, density 1e-3 ({nnz} nonzeros), k={k}, {T} iterations per step, "
-                       f"FP32 SpMM, FP64 Gram/BPP, cold BPP"}
-    res.update(form(L.NMF_WARM_COLD))
-    res["warm_prev"] = form(L.NMF_WARM_PREV)
-    res["warm_prev"]["abs_dr_vs_cold"] = abs(res["warm_prev"]["final_r"] - res["final_r"])
-    print(json.dumps({"sparse": res}))
+KS = (10, 20, 30, 40, 50)
 
 
 def ksweep_mode(a):
@@ -637,25 +945,8 @@ def ksweep_mode(a):
         for k in KS:
             W0, Ht0 = gen.init_factors(seed, m, n, k)
             W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
-            run = L.Anls(M, k, L.make_opts(trace=True, reset_masks=True, **kw))
-            stats = L.new_stats(T)
-
-            def step(timer=None):
-                W.copy_(W0)
-                Ht.copy_(Ht0)
-                if timer:
-                    timer.attach(run.opts)
-                run.run(W, Ht, T, stats)
-                if timer:
-                    timer.detach(run.opts)
-
-            t = timed(step, a.steps, a.warmup)
+            t, ph, _ = _form_run(L, M, k, W, Ht, W0, Ht0, T, a.steps, a.warmup, **kw)
             r = float(L.nmf_objective(M, W, Ht)[0])
-            tm = L.PhaseTimer(T)
-            step(tm)
-            torch.cuda.synchronize()
-            ph = {p: float(np.mean(v)) for p, v in tm.phase_ms().items()}
-            tm.close()
             o = o_s = None
             if ref is not None and name.startswith("bpp"):
                 o = ref["k"][str(k)]["r_full"][-1]
@@ -674,11 +965,12 @@ def ksweep_mode(a):
                          "mm_GBps": mm_gbs, "mm_hbm_frac": mm_gbs / 8000.0, "oracle_s_per_iter_recorded": o_s})
             print(f"# {name} k={k}: {ms:.2f} ms/iter (MM {split['MM']:.2f} at {mm_gbs:.0f} GB/s, "
                   f"NLS {split['NLS']:.2f}, Gram {split['Gram']:.2f}), r {r:.8f}", file=sys.stderr, flush=True)
-            del run, W, Ht, W0, Ht0
+            del W, Ht, W0, Ht0
         out["forms"][name] = rows
     print(json.dumps({"ksweep": out}))
 
 
+# -------------------------------------------------------------------- main --
 def main():
     a = parse()
     if a.gpus != 1:
@@ -692,17 +984,21 @@ def main():
         pmc_bpp_mode(a)
         return
     if a.sparse:
-        sparse_mode(a)
+        print(json.dumps({"sparse": sparse_workload(a, a.steps, a.warmup, with_cpu=not a.no_cpu_baseline)}))
         return
     if a.ksweep:
         ksweep_mode(a)
         return
     if a.dense:
-        dense_mode(a)
+        print(json.dumps({"dense": dense_workload(a, a.steps, a.warmup, with_cpu=not a.no_cpu_baseline)}))
         return
     import numpy as np
+    import torch
     b = Bench(a)
     L = b.L
+    ref = load_golden()
+    if ref is not None and (a.m, a.n, a.k, a.iters) != (1_000_000, 2_400, 30, 50):
+        ref = None
     print(f"# inputs: generate {b.t_gen:.2f}s, one-time BF16 split {b.t_split:.3f}s", file=sys.stderr, flush=True)
 
     # learned + BF16x3 form, with per-phase events over the timed steps
@@ -710,51 +1006,58 @@ def main():
     it = iter(timers)
     for _ in range(a.warmup):
         b.learned_step()
-    b.torch.cuda.synchronize()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(a.steps):
         b.learned_step(next(it))
-    b.torch.cuda.synchronize()
+    torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     r_learned = b.final_r()
+    agree_learned = passive_set_agreement(b.W, b.Ht, ref, a.k)
     st_l = L.decode_stats(b.st1) + L.decode_stats(b.st2)
     print(f"# learned+bf16x3: {t_learned / a.steps * 1e3:.1f} ms/step, final r {r_learned:.8f}", file=sys.stderr,
           flush=True)
-    roof = roofline(b, [t for pair in timers for t in pair], [L.decode_stats(b.st1), L.decode_stats(b.st2)])
+    ph_l = mean_phases([t for pair in timers for t in pair])
+    # per-iteration phase lists of the last timed step (iterations 1..iters)
+    p1, p2 = timers[-1][0].phase_ms(), timers[-1][1].phase_ms()
+    per_iter_l = {p: p1[p] + p2[p] for p in L.PHASES}
+    roof = roofline(ph_l, {}, a.m, a.n, a.k, "bf16x3", "dense", st_l)
+    roof["phase_ms_per_iter"] = ph_l
 
     plain = None
     if not a.no_plain:
         tp = L.PhaseTimer(a.iters)
         t_plain = timed(b.plain_step, a.steps, a.warmup)
         r_plain = b.final_r()
+        agree_plain = passive_set_agreement(b.W, b.Ht, ref, a.k)
         b.plain_step(tp)
-        b.torch.cuda.synchronize()
-        ph = tp.phase_ms()
+        torch.cuda.synchronize()
+        ph = mean_phases([tp])
+        tp.close()
         st_p = L.decode_stats(b.stP)
         plain = {"iters_per_s": a.iters * a.steps / t_plain, "ms_per_step": t_plain / a.steps * 1e3,
-                 "final_r": r_plain, "phase_ms_per_iter": {p: float(np.mean(v)) for p, v in ph.items()},
+                 "final_r": r_plain, "abs_dr_vs_oracle": None if ref is None else abs(r_plain - ref["r_full"][-1]),
+                 "phase_ms_per_iter": ph,
+                 "products_mfma": products_mfma(ph, a.m, a.n, a.k, "fp32"),
+                 "roofline": roofline(ph, {}, a.m, a.n, a.k, "fp32", "dense", st_p, workload="video_fp32"),
+                 "passive_set_agreement": agree_plain,
                  "bpp_rounds_w_per_row": float(np.mean([s["bpp_w"][0] for s in st_p]) / a.m),
                  "bpp_solves_w_per_row": float(np.mean([s["bpp_w"][1] for s in st_p]) / a.m)}
         print(f"# plain fp32: {plain['ms_per_step']:.1f} ms/step, final r {r_plain:.8f}", file=sys.stderr, flush=True)
 
-    oracle_r = None
-    if os.path.exists(GOLDEN) and (a.m, a.n, a.k, a.iters) == (1_000_000, 2_400, 30, 50):
-        with open(GOLDEN) as fh:
-            oracle_r = json.load(fh)["r_full"][-1]
+    warm = None
+    if not a.no_warm_starts:
+        warm = warm_start_forms(b, ref, per_iter_l, st_l)
+
+    oracle_r = None if ref is None else ref["r_full"][-1]
 
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(b, a.cpu_seconds)
+        cpu = cpu_baseline_video(b, a.cpu_seconds)
 
     loc = None
     if not a.no_local:
         loc = local_forms(b)
-
-    bat = None
-    if not a.no_batched:
-        bat = batched(a)
-        print(f"# batched 256 instances: {bat['ms_per_30_iterations']:.1f} ms per 30 iterations", file=sys.stderr,
-              flush=True)
 
     value = a.iters * a.steps / t_learned
     res = {
@@ -778,6 +1081,8 @@ def main():
         "final_r": r_learned,
         "oracle_r": oracle_r,
         "abs_dr_vs_oracle": None if oracle_r is None else abs(r_learned - oracle_r),
+        "passive_set_agreement": agree_learned,
+        "products_mfma": products_mfma(ph_l, a.m, a.n, a.k, "bf16x3"),
         "plain_fp32": plain,
         "speedup_vs_plain_fp32": None if plain is None else value / plain["iters_per_s"],
         "matched_objective": None if plain is None else (
@@ -788,12 +1093,26 @@ def main():
         "one_time_split_s": b.t_split,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "warm_starts": warm,
         "local_solvers": loc,
-        "batched": bat,
     }
     for pair in timers:
         for t in pair:
             t.close()
+    # free the headline workload (A, both BF16 orientations: 29 GB) before the others
+    del b
+    torch.cuda.empty_cache()
+
+    if not a.no_batched:
+        res["batched"] = batched(a)
+        print(f"# batched 256 instances: {res['batched']['ms_per_30_iterations']:.1f} ms per 30 iterations",
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    if not a.no_dense:
+        res["dense"] = dense_workload(a, a.sub_steps, a.sub_warmup, with_cpu=not a.no_cpu_baseline)
+        torch.cuda.empty_cache()
+    if not a.no_sparse:
+        res["sparse"] = sparse_workload(a, a.sub_steps, a.sub_warmup, with_cpu=not a.no_cpu_baseline)
     print(json.dumps(res))
 
 

@@ -60,6 +60,7 @@ extern "C" {
 #define NMF_WARM_COLD 0     /* every BPP starts from the empty passive set */
 #define NMF_WARM_PREV 1     /* start from the previous iteration's passive set */
 #define NMF_WARM_LEARNED 2  /* start from the warm-start network's prediction */
+#define NMF_WARM_ALL 3      /* start from the full set (every unpinned index passive) */
 
 /* local NLS solver of Algorithm 1 (nmf_opts.solver, nmf_local_update) */
 #define NMF_SOLVER_BPP 0    /* block principal pivoting (the exact NNLS solution) */
@@ -268,7 +269,7 @@ int nmf_objective(const nmf_matrix* A, int k, const float* W, const float* Ht, i
 /* ---- the ANLS driver --------------------------------------------------------- */
 typedef struct nmf_opts {
   int prec;             /* NMF_F32 or NMF_BF16X3 (dense only) */
-  int warm;             /* NMF_WARM_COLD / NMF_WARM_PREV / NMF_WARM_LEARNED */
+  int warm;             /* NMF_WARM_COLD / NMF_WARM_PREV / NMF_WARM_LEARNED / NMF_WARM_ALL */
   int max_rounds;       /* BPP round cap (e.g. 100) */
   int warm_cap;         /* rounds a warm start gets before its cold restart */
   int trace_objective;  /* 1: record r after each half-step (TRACE, FP64) */

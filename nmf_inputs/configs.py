@@ -147,19 +147,22 @@ def init_ht(seed: int, n: int, k: int, inst: int | None = None, cols=None) -> np
 # sparse matrices (config 3)
 # ----------------------------------------------------------------------------
 
-def sparse_csr(seed: int, m: int, n: int, density: float, inst: int | None = None):
+def sparse_csr(seed: int, m: int, n: int, density: float, inst: int | None = None, workers: int = 1):
     """Erdos-Renyi CSR: every entry is nonzero independently with prob. `density`.
 
     Row i's positions come from geometric gaps g_t = floor(log(u_t)/log(1-p)),
     u_t in (0,1] from the row's own Philox stream (counter (i, t)).  Returns
     (rowptr int64[m+1], colidx int32[nnz], vals float32[nnz]); columns sorted.
+    workers > 1 builds the row chunks on that many host threads (the result
+    does not depend on it).
     """
     lp = math.log1p(-density)
     mean = n * density
     t_cap = int(mean + 8.0 * math.sqrt(mean + 1.0) + 16)
-    rows_cols, rows_vals, counts = [], [], np.zeros(m, dtype=np.int64)
+    counts = np.zeros(m, dtype=np.int64)
     chunk = max(1, min(m, 2_000_000 // max(t_cap, 1)))
-    for r0 in range(0, m, chunk):
+
+    def rows_chunk(r0):
         r1 = min(m, r0 + chunk)
         nr = r1 - r0
         t = t_cap
@@ -171,11 +174,19 @@ def sparse_csr(seed: int, m: int, n: int, density: float, inst: int | None = Non
                 break
             t *= 2
         keep = pos < n
-        cnt = keep.sum(axis=1)
-        counts[r0:r1] = cnt
+        counts[r0:r1] = keep.sum(axis=1)
         vals = 1.0 - uniform(seed, mid(MID_VAL, inst), r0, nr, 0, t)
-        rows_cols.append(pos[keep].astype(np.int32))
-        rows_vals.append(vals[keep].astype(np.float32))
+        return pos[keep].astype(np.int32), vals[keep].astype(np.float32)
+
+    starts = range(0, m, chunk)
+    if workers > 1:
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            parts = list(ex.map(rows_chunk, starts))
+    else:
+        parts = [rows_chunk(r0) for r0 in starts]
+    rows_cols = [p[0] for p in parts]
+    rows_vals = [p[1] for p in parts]
     rowptr = np.zeros(m + 1, dtype=np.int64)
     np.cumsum(counts, out=rowptr[1:])
     colidx = np.concatenate(rows_cols) if rows_cols else np.zeros(0, np.int32)

@@ -67,6 +67,10 @@ def lib():
                                vp, vp, vp]
         L.orc_anls.restype = ci
         L.orc_max_threads.restype = ci
+        L.orc_set_threads.argtypes = [ci]
+        L.orc_set_threads.restype = None
+        L.orc_last_phase_seconds.argtypes = [vp]
+        L.orc_last_phase_seconds.restype = None
         _lib = L
     return _lib
 
@@ -220,12 +224,20 @@ def anls(k, W0, Ht0, T, *, dense=None, csr=None, csr_t=None, shape=None, max_rou
                         _p(r_half), _p(r_full), _p(rw), _p(rh), ctypes.byref(cap), _p(mw), _p(mh))
     if rc != 0:
         raise MemoryError("oracle ANLS could not allocate its buffers")
+    ph = np.zeros(6)
+    lib().orc_last_phase_seconds(_p(ph))
     return dict(W=W, Ht=Ht, r_half=r_half, r_full=r_full, rounds_w=rw, rounds_h=rh,
-                capped=int(cap.value), masks_w=mw, masks_h=mh, fro2=fro2)
+                capped=int(cap.value), masks_w=mw, masks_h=mh, fro2=fro2,
+                phase_seconds=dict(zip(("rhs_w", "bpp_w", "gram", "rhs_h", "bpp_h", "objective"), ph.tolist())))
 
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def kkt_residuals(G, f, x):

@@ -31,6 +31,7 @@
  *   - a warm start that has not converged within `warm_cap` rounds restarts
  *     from the empty passive set (status WARM_FALLBACK).
  */
+#include <omp.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -362,10 +363,21 @@ static double dot(int64_t len, const double* a, const double* b) {
  * iteration's passive set of the same row/column (same unique solution).
  * rounds_w / rounds_h (optional, T entries) receive the total BPP rounds per
  * half-step; masks_w / masks_h (optional) receive the final passive sets. */
+/* Wall seconds of the last orc_anls call by phase (timing only):
+ * [0] A H^T, [1] BPP for W, [2] both Gram products, [3] W^T A, [4] BPP for H,
+ * [5] the objective sums. */
+static double g_phase[6];
+void orc_last_phase_seconds(double* out) {
+  for (int i = 0; i < 6; ++i) out[i] = g_phase[i];
+}
+
 int orc_anls(const orc_matrix* A, int k, double* W, double* Ht, int T, int max_rounds, int warm,
              int warm_cap, double fro2_A, double* r_half, double* r_full, int64_t* rounds_w,
              int64_t* rounds_h, int64_t* capped, uint64_t* masks_w, uint64_t* masks_h) {
   const int64_t m = A->m, n = A->n;
+  for (int i = 0; i < 6; ++i) g_phase[i] = 0.0;
+  double tw = omp_get_wtime(), tn;
+#define ORC_PHASE(i) (tn = omp_get_wtime(), g_phase[i] += tn - tw, tw = tn)
   double* RW = (double*)malloc(sizeof(double) * (size_t)m * k);
   double* RH = (double*)malloc(sizeof(double) * (size_t)n * k);
   uint64_t* MW = (uint64_t*)calloc((size_t)m, sizeof(uint64_t));
@@ -378,28 +390,38 @@ int orc_anls(const orc_matrix* A, int k, double* W, double* Ht, int T, int max_r
   for (int t = 0; t < T; ++t) {
     /* W <- argmin_{W>=0} ||A - W H||  via  H H^T and A H^T */
     orc_gram(n, k, Ht, k, GH);
+    ORC_PHASE(2);
     rhs_w(A, k, Ht, RW);
+    ORC_PHASE(0);
     orc_bpp_batched(k, m, GH, RW, W, warm ? MW : NULL, MW, rnd, sts, max_rounds, warm_cap);
     int64_t s = 0;
     for (int64_t i = 0; i < m; ++i) { s += rnd[i]; ncap += (sts[i] & ORC_ST_CAPPED) != 0; }
     if (rounds_w) rounds_w[t] = s;
+    ORC_PHASE(1);
     orc_gram(m, k, W, k, GW);
+    ORC_PHASE(2);
     if (r_half) {
       double r2 = fro2_A - 2.0 * dot(m * k, RW, W) + dot(k * k, GW, GH);
       r_half[t] = sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(fro2_A);
     }
+    ORC_PHASE(5);
     /* H <- argmin_{H>=0} ||A - W H||  via  W^T W and W^T A */
     rhs_h(A, k, W, RH);
+    ORC_PHASE(3);
     orc_bpp_batched(k, n, GW, RH, Ht, warm ? MH : NULL, MH, rnd, sts, max_rounds, warm_cap);
     s = 0;
     for (int64_t j = 0; j < n; ++j) { s += rnd[j]; ncap += (sts[j] & ORC_ST_CAPPED) != 0; }
     if (rounds_h) rounds_h[t] = s;
+    ORC_PHASE(4);
     orc_gram(n, k, Ht, k, GH);
+    ORC_PHASE(2);
     if (r_full) {
       double r2 = fro2_A - 2.0 * dot(n * k, RH, Ht) + dot(k * k, GW, GH);
       r_full[t] = sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(fro2_A);
     }
+    ORC_PHASE(5);
   }
+#undef ORC_PHASE
   if (capped) *capped = ncap;
   if (masks_w) memcpy(masks_w, MW, sizeof(uint64_t) * (size_t)m);
   if (masks_h) memcpy(masks_h, MH, sizeof(uint64_t) * (size_t)n);
@@ -408,5 +430,6 @@ int orc_anls(const orc_matrix* A, int k, double* W, double* Ht, int T, int max_r
 }
 
 /* Threads the OpenMP loops above use (reported with the CPU baseline). */
-#include <omp.h>
 int orc_max_threads(void) { return omp_get_max_threads(); }
+/* Thread count of the parallel loops (for timing the oracle at 1 thread). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

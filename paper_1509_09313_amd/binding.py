@@ -18,7 +18,7 @@ NMF_F32, NMF_BF16X3 = 0, 1
 NMF_SIDE_W, NMF_SIDE_H = 0, 1
 NMF_DENSE, NMF_CSR = 0, 1
 NMF_OBJ_DIRECT, NMF_OBJ_TRACE = 0, 1
-NMF_WARM_COLD, NMF_WARM_PREV, NMF_WARM_LEARNED = 0, 1, 2
+NMF_WARM_COLD, NMF_WARM_PREV, NMF_WARM_LEARNED, NMF_WARM_ALL = 0, 1, 2, 3
 NMF_SOLVER_BPP, NMF_SOLVER_HALS, NMF_SOLVER_MU = 0, 1, 2
 NMF_BPP_WARM_FALLBACK, NMF_BPP_CAPPED, NMF_BPP_PINNED, NMF_BPP_SINGULAR = 1, 2, 4, 8
 NMF_BPP_COUNTERS = 6

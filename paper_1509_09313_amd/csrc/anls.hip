@@ -27,6 +27,20 @@ __global__ void k_zero_u64(uint64_t* __restrict__ p, int64_t n) {
     p[e] = 0;
 }
 
+__global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// NMF_WARM_ALL: every problem of the next BPP launch starts from the full set
+int fill_full_sets(uint64_t* masks, int64_t n, int k, hipStream_t s) {
+  const uint64_t full = k >= 64 ? ~0ull : ((1ull << k) - 1ull);
+  int64_t blocks = nmf::cdiv(n, 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, masks, n, full);
+  return nmf::launch_status("full start sets");
+}
+
 __global__ void k_status_count(int64_t n, const uint8_t* __restrict__ status, unsigned long long* __restrict__ capped,
                                unsigned long long* __restrict__ fallback) {
   __shared__ unsigned long long s[2][256];
@@ -117,7 +131,7 @@ int check_opts(const nmf_matrix* A, const nmf_opts* o) {
     return nmf::fail(NMF_EINVAL, "nmf_anls: BF16X3 needs a dense matrix");
   if (o->prec == NMF_BF16X3 && (!A->A_bf16 || !A->At_bf16))
     return nmf::fail(NMF_EINVAL, "nmf_anls: BF16X3 needs the tiled BF16 forms of A and A^T");
-  if (o->warm < NMF_WARM_COLD || o->warm > NMF_WARM_LEARNED) return nmf::fail(NMF_EINVAL, "nmf_anls: bad warm mode");
+  if (o->warm < NMF_WARM_COLD || o->warm > NMF_WARM_ALL) return nmf::fail(NMF_EINVAL, "nmf_anls: bad warm mode");
   if (o->warm == NMF_WARM_LEARNED && (!o->net_w || !o->net_h))
     return nmf::fail(NMF_EINVAL, "nmf_anls: learned warm start needs both networks");
   if (o->max_rounds < 1 || o->warm_cap < 1) return nmf::fail(NMF_EINVAL, "nmf_anls: max_rounds/warm_cap < 1");
@@ -255,6 +269,7 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     rec(ev(t, NMF_PH_INFER_W, 0));
     if (o->warm == NMF_WARM_LEARNED)
       NMF_TRY(nmf::mlp_infer_launch(k, m, P.GH, P.RW, k, o->net_w, P.MW, P.infer_w, s));
+    if (o->warm == NMF_WARM_ALL) NMF_TRY(fill_full_sets(P.MW, m, k, s));
     rec(ev(t, NMF_PH_INFER_W, 1));
     rec(ev(t, NMF_PH_BPP_W, 0));
     if (o->solver == NMF_SOLVER_BPP) {
@@ -283,6 +298,7 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     rec(ev(t, NMF_PH_INFER_H, 0));
     if (o->warm == NMF_WARM_LEARNED)
       NMF_TRY(nmf::mlp_infer_launch(k, n, P.GW, P.RH, k, o->net_h, P.MH, P.infer_h, s));
+    if (o->warm == NMF_WARM_ALL) NMF_TRY(fill_full_sets(P.MH, n, k, s));
     rec(ev(t, NMF_PH_INFER_H, 1));
     rec(ev(t, NMF_PH_BPP_H, 0));
     if (o->solver == NMF_SOLVER_BPP) {

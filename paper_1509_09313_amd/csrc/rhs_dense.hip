@@ -8,12 +8,14 @@
 // A or columns of A).  The contraction index inside one K-chunk is permuted
 // freely (A and B operands use the same permutation) so that every lane's
 // operand comes from one 16-byte load.
-//   side W stages 128 x 32 tiles of A in LDS (rows of A are contracted
-//     along their contiguous dimension, so lanes need different rows);
+//   side W stages 128 x 32 tiles of A and of the transposed Y in LDS (rows of
+//     A are contracted along their contiguous dimension, so lanes need
+//     different rows), two chunks in flight;
 //   side H needs no LDS: lane (j, h) loads A[r + h][c0 + 4j .. +3] with one
 //     16-byte load (a 512-byte contiguous segment per half-wave) and feeds
-//     four MFMAs, one per component; the rows of A are split into S ranges
-//     whose FP32 partials are summed in FP64 in a fixed order.
+//     four MFMAs, one per component, with the next rows' loads issued before
+//     the current rows' MFMAs; the rows of A are split into S ranges whose
+//     FP32 partials are summed in FP64 in a fixed order.
 // BF16X3 path (tiled BF16 operand): see rhs_bf16.hip.
 #include "nmf_common.h"
 
@@ -137,6 +139,188 @@ __global__ __launch_bounds__(256) void k_rhs_w_f32(int64_t m, int64_t n, int k, 
   }
 }
 
+// Side W, streaming form (A 16-byte aligned with lda % 4 == 0): the
+// structure of the BF16x3 product kernel with FP32 operands.  Each block owns
+// 128 rows of A and walks the contraction in 32-column chunks (16 KB of A per
+// chunk: small staging sets give three blocks per CU; 64-column chunks, two
+// blocks per CU, measured 8% slower); Y comes transposed and zero-padded (Yt,
+// KP x ldt with ldt a multiple of 64), so a lane reads
+// four consecutive contraction indices of its Y column as one 16-byte LDS
+// read, as it does for its row of A.  Two chunks are in flight in two register
+// staging sets, with unconditional loads (rows past m are clamped to m - 1:
+// a row only feeds its own output row, which is not stored) so each wait is
+// for the older set only.  A ragged last chunk (n not a multiple of 64) is
+// loaded element by element with zeros past n.  The finished tile leaves
+// through LDS as whole rows.
+constexpr int kSC = 32;            // contraction chunk (columns of A)
+constexpr int kSPitch = kSC + 4;   // LDS pitch in floats (== 4 mod 32: conflict-free 16-byte reads)
+constexpr int kSRowsPass = 256 / (kSC / 4);  // rows one staging pass covers
+constexpr int kSPassA = kWTM / kSRowsPass;   // passes over the 128-row A tile
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_rhs_w_f32s(int64_t m, int64_t n, int k, const float* __restrict__ A,
+                                                    int64_t lda, const float* __restrict__ Yt, int64_t ldt,
+                                                    float* __restrict__ R, int64_t ldr) {
+  constexpr int KP = 32 * NT;
+  constexpr int kPassY = KP / kSRowsPass;
+  __shared__ __align__(16) float As[kWTM * kSPitch];
+  __shared__ __align__(16) float Ys[KP * kSPitch];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int j = lane & 31, h = lane >> 5;
+  const int64_t row0 = (int64_t)blockIdx.x * kWTM;
+  const int64_t nfull = n / kSC;  // whole chunks
+
+  v16f acc[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) acc[tt] = v16f{};
+
+  // thread t stages rows lr + kSRowsPass s of the tile, columns lc .. lc + 3
+  const int lr = t / (kSC / 4), lc = 4 * (t % (kSC / 4));
+  const int64_t rlast = m - 1 - row0;
+  const float* a_base = A + (row0 + lr) * lda + lc;
+  struct Stage {
+    float4 a[kSPassA];
+    float4 y[kPassY];
+  };
+  // row lr + kSRowsPass s of the tile, clamped to the last row of A
+  auto arow = [&](int s) __attribute__((always_inline)) -> const float* {
+    const int r = lr + kSRowsPass * s;
+    return r <= rlast ? a_base + (int64_t)kSRowsPass * s * lda : a_base + (rlast - lr) * lda;
+  };
+  auto load = [&](Stage& S, int64_t c0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < kSPassA; ++s) S.a[s] = load_stream(arow(s) + c0);
+    const float* yp = Yt + (int64_t)lr * ldt + c0 + lc;
+#pragma unroll
+    for (int s = 0; s < kPassY; ++s) S.y[s] = *reinterpret_cast<const float4*>(yp + (int64_t)kSRowsPass * s * ldt);
+  };
+  // the ragged last chunk: element loads, zero past column n
+  auto load_tail = [&](Stage& S, int64_t c0) __attribute__((always_inline)) {
+    const int64_t c = c0 + lc;
+#pragma unroll
+    for (int s = 0; s < kSPassA; ++s) {
+      const float* p = arow(s) + c0;
+      S.a[s].x = c + 0 < n ? p[0] : 0.0f;
+      S.a[s].y = c + 1 < n ? p[1] : 0.0f;
+      S.a[s].z = c + 2 < n ? p[2] : 0.0f;
+      S.a[s].w = c + 3 < n ? p[3] : 0.0f;
+    }
+    const float* yp = Yt + (int64_t)lr * ldt + c0 + lc;
+#pragma unroll
+    for (int s = 0; s < kPassY; ++s) S.y[s] = *reinterpret_cast<const float4*>(yp + (int64_t)kSRowsPass * s * ldt);
+  };
+  const int so = lr * kSPitch + lc;
+  auto store = [&](const Stage& S) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < kSPassA; ++s) *reinterpret_cast<float4*>(&As[so + kSRowsPass * s * kSPitch]) = S.a[s];
+#pragma unroll
+    for (int s = 0; s < kPassY; ++s) *reinterpret_cast<float4*>(&Ys[so + kSRowsPass * s * kSPitch]) = S.y[s];
+  };
+  // lane (j, h) takes contraction indices 8 g + 4 h + q for the q-th MFMA of
+  // group g, for A and Y alike
+  auto compute = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int g = 0; g < kSC / 8; ++g) {
+      const int off = 8 * g + 4 * h;
+      const float4 a4 = *reinterpret_cast<const float4*>(&As[(32 * w + j) * kSPitch + off]);
+      const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) {
+        const float4 y4 = *reinterpret_cast<const float4*>(&Ys[(32 * tt + j) * kSPitch + off]);
+        const float yv[4] = {y4.x, y4.y, y4.z, y4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[tt] = mfma32(yv[q], av[q], acc[tt]);
+      }
+    }
+  };
+  if (nfull >= 4) {
+    Stage S0, S1;
+    load(S0, 0);
+    __builtin_amdgcn_sched_barrier(0);  // same issue order as in the loop
+    load(S1, kSC);
+    int64_t c = 0;
+    for (; c + 3 < nfull; c += 2) {
+      __syncthreads();
+      store(S0);
+      __syncthreads();
+      load(S0, (c + 2) * kSC);
+      compute();
+      __syncthreads();
+      store(S1);
+      __syncthreads();
+      load(S1, (c + 3) * kSC);
+      compute();
+    }
+    const bool three = c + 2 < nfull;
+    __syncthreads();
+    store(S0);
+    __syncthreads();
+    if (three) load(S0, (c + 2) * kSC);
+    compute();
+    __syncthreads();
+    store(S1);
+    __syncthreads();
+    compute();
+    if (three) {
+      __syncthreads();
+      store(S0);
+      __syncthreads();
+      compute();
+    }
+  } else {
+    Stage S0;
+    if (nfull > 0) load(S0, 0);
+    for (int64_t c = 0; c < nfull; ++c) {
+      __syncthreads();
+      store(S0);
+      __syncthreads();
+      if (c + 1 < nfull) load(S0, (c + 1) * kSC);
+      compute();
+    }
+  }
+  if (nfull * kSC < n) {
+    Stage S0;
+    load_tail(S0, nfull * kSC);
+    __syncthreads();
+    store(S0);
+    __syncthreads();
+    compute();
+  }
+  // D_tt[i][j] = R[row0 + 32w + j][32 tt + i]; lane holds i = (v&3) + 8(v>>2) + 4h.
+  // Each 32-column part leaves through LDS as whole row segments.
+  constexpr int OP = 33;  // odd pitch: conflict-free column writes
+  static_assert(kWTM * OP <= kWTM * kSPitch, "output part exceeds the staging buffer");
+  const int nr = m - row0 < kWTM ? (int)(m - row0) : kWTM;
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    const int cw = k - 32 * tt < 32 ? k - 32 * tt : 32;  // columns of this part
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 16; ++v) As[(32 * w + j) * OP + (v & 3) + 8 * (v >> 2) + 4 * h] = acc[tt][v];
+    __syncthreads();
+    for (int e = t; e < nr * cw; e += 256) {
+      const int row = e / cw, c = e - row * cw;
+      R[(row0 + row) * ldr + 32 * tt + c] = As[row * OP + c];
+    }
+  }
+}
+
+// Yt (KP x ldt) = Y^T (Y: K x k, ld ldy), zero in rows >= k and columns >= K.
+__global__ __launch_bounds__(256) void k_transpose_y(int64_t K, int k, int KP, const float* __restrict__ Y,
+                                                     int64_t ldy, float* __restrict__ Yt, int64_t ldt) {
+  __shared__ float tile[64][65];
+  const int64_t K0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int kk = e / 64, c = e - kk * 64;
+    tile[kk][c] = (K0 + kk < K && c < k) ? Y[(K0 + kk) * ldy + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < KP * 64; e += 256) {
+    const int i = e / 64, kk = e - i * 64;
+    Yt[i * ldt + K0 + kk] = tile[kk][i];
+  }
+}
+
 // ---------------------------------------------------------------- side H --
 constexpr int kHCols = 128;  // columns of A per wave
 constexpr int kHUnroll = 8;  // row pairs in flight per lane
@@ -214,6 +398,102 @@ __global__ __launch_bounds__(64) void k_rhs_h_f32(int64_t m, int64_t n, int k, c
   }
 }
 
+// Side H, streaming form (A 16-byte aligned with lda % 4 == 0): the same
+// per-lane scheme as k_rhs_h_f32 with the loads of the next 16 rows issued
+// before the MFMAs of the current ones (two register sets).  Every load is
+// unconditional: rows are clamped to m - 1, columns past n to the row's last
+// 16-byte segment and Y columns past k to k - 1, all valid addresses.  A row
+// outside [r_begin, r_end) or a Y column past k then gets a zero Y value, so
+// it adds nothing (an entry of A only meets its own column's outputs, and
+// outputs past n are not stored).
+constexpr int kHSU = 8;  // row pairs per register set of the streaming form
+
+template <int NT>
+struct HSet {
+  float4 a[kHSU];
+  float y[kHSU][NT];
+};
+
+template <int NT>
+__device__ __forceinline__ void h_load(HSet<NT>& S, const float* __restrict__ A, int64_t lda,
+                                       const float* __restrict__ Y, int64_t ldy, int64_t r, int64_t m, int64_t colc,
+                                       int h, int j, int k) {
+#pragma unroll
+  for (int u = 0; u < kHSU; ++u) {
+    const int64_t rr = r + 2 * u + h;
+    const int64_t rc = rr < m ? rr : m - 1;
+    S.a[u] = load_stream(A + rc * lda + colc);
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int c = 32 * tt + j;
+      S.y[u][tt] = Y[rc * ldy + (c < k ? c : k - 1)];
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void h_compute(const HSet<NT>& S, v16f (&acc)[4][NT], int64_t r, int64_t r_end, int h,
+                                          int j, int k) {
+#pragma unroll
+  for (int u = 0; u < kHSU; ++u) {
+    const bool rok = r + 2 * u + h < r_end;
+    const float av[4] = {S.a[u].x, S.a[u].y, S.a[u].z, S.a[u].w};
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const float yv = (rok && 32 * tt + j < k) ? S.y[u][tt] : 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q][tt] = mfma32(yv, av[q], acc[q][tt]);
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(64) void k_rhs_h_f32s(int64_t m, int64_t n, int k, const float* __restrict__ A,
+                                                   int64_t lda, const float* __restrict__ Y, int64_t ldy,
+                                                   float* __restrict__ P, int64_t ldp, int64_t rows_per_split,
+                                                   int64_t split_stride, int64_t ngroups, int64_t nsplit) {
+  const int64_t per_xcd = gridDim.x / 8;
+  const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (lid >= ngroups * nsplit) return;
+  const int64_t gx = lid % ngroups, gy = lid / ngroups;
+  const int lane = threadIdx.x;
+  const int j = lane & 31, h = lane >> 5;
+  const int64_t col = gx * kHCols + 4 * j;
+  const int64_t colc = col < lda - 3 ? col : lda - 4;
+  const int64_t r_begin = gy * rows_per_split;
+  const int64_t r_end = (r_begin + rows_per_split < m) ? r_begin + rows_per_split : m;
+
+  v16f acc[4][NT];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[q][tt] = v16f{};
+
+  constexpr int kG = 2 * kHSU;  // rows per register set
+  HSet<NT> S0, S1;
+  h_load<NT>(S0, A, lda, Y, ldy, r_begin, m, colc, h, j, k);
+  h_load<NT>(S1, A, lda, Y, ldy, r_begin + kG, m, colc, h, j, k);
+  for (int64_t r = r_begin; r < r_end; r += 2 * kG) {
+    h_compute<NT>(S0, acc, r, r_end, h, j, k);
+    h_load<NT>(S0, A, lda, Y, ldy, r + 2 * kG, m, colc, h, j, k);
+    h_compute<NT>(S1, acc, r + kG, r_end, h, j, k);
+    h_load<NT>(S1, A, lda, Y, ldy, r + 3 * kG, m, colc, h, j, k);
+  }
+  float* out = P + gy * split_stride;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t row = col + q;
+    if (row >= n) continue;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int c = 32 * tt + (v & 3) + 8 * (v >> 2) + 4 * h;
+        if (c < k) out[row * ldp + c] = acc[q][tt][v];
+      }
+  }
+}
+
 // R[row][c] = sum_s P[s][row][c], summed in FP64 in split order.
 __global__ void k_split_reduce(int64_t n, int k, int S, const float* __restrict__ P, int64_t split_stride,
                                float* __restrict__ R, int64_t ldr) {
@@ -235,7 +515,7 @@ struct HSplit {
 HSplit h_split(int64_t m, int64_t n) {
   HSplit s;
   s.colgroups = nmf::cdiv(n, kHCols);
-  const int64_t target_waves = 3072;
+  const int64_t target_waves = 4096;
   int64_t S = nmf::cdiv(target_waves, s.colgroups);
   const int64_t max_s = m / 512 > 1 ? m / 512 : 1;
   if (S > max_s) S = max_s;
@@ -249,16 +529,28 @@ HSplit h_split(int64_t m, int64_t n) {
   return s;
 }
 
+// Leading dimension of the transposed, padded Y of the streaming side-W kernel:
+// whole 64-column blocks of the transposition kernel, whole chunks of the product.
+static_assert(64 % kSC == 0, "a transposition block covers whole chunks");
+int64_t w_yt_ld(int64_t n) { return nmf::cdiv(n, 64) * 64; }
+
+bool w_streaming(const float* A, int64_t lda) { return (lda % 4 == 0) && ((uintptr_t)A % 16 == 0); }
+
 template <int NT>
 int launch_w_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const float* Y, int64_t ldy,
-                 float* R, int64_t ldr, hipStream_t s) {
-  const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+                 float* R, int64_t ldr, float* yt, hipStream_t s) {
   const dim3 grid((unsigned)nmf::cdiv(m, kWTM));
+  if (w_streaming(A, lda)) {
+    const int64_t ldt = w_yt_ld(n);
+    hipLaunchKernelGGL(k_transpose_y, dim3((unsigned)(ldt / 64)), dim3(256), 0, s, n, k, 32 * NT, Y, ldy, yt, ldt);
+    NMF_TRY(nmf::launch_status("rhs side W (fp32): transpose Y"));
+    nmf::mark_begin(s);
+    hipLaunchKernelGGL((k_rhs_w_f32s<NT>), grid, dim3(256), 0, s, m, n, k, A, lda, yt, ldt, R, ldr);
+    nmf::mark_end(s);
+    return nmf::launch_status("rhs side W (fp32)");
+  }
   nmf::mark_begin(s);
-  if (vec)
-    hipLaunchKernelGGL((k_rhs_w_f32<NT, true>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
-  else
-    hipLaunchKernelGGL((k_rhs_w_f32<NT, false>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
+  hipLaunchKernelGGL((k_rhs_w_f32<NT, false>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
   nmf::mark_end(s);
   return nmf::launch_status("rhs side W (fp32)");
 }
@@ -273,7 +565,10 @@ int launch_h_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const
   const int64_t stride = sp.S > 1 ? n * k : 0;
   const dim3 grid((unsigned)(nmf::cdiv(sp.colgroups * sp.S, 8) * 8));
   nmf::mark_begin(s);
-  if (vec)
+  if (vec && n >= 4)
+    hipLaunchKernelGGL((k_rhs_h_f32s<NT>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
+                       sp.rows_per_split, stride, sp.colgroups, (int64_t)sp.S);
+  else if (vec)
     hipLaunchKernelGGL((k_rhs_h_f32<NT, true>), grid, dim3(64), 0, s, m, n, k, A, lda, Y, ldy, P, ldp,
                        sp.rows_per_split, stride, sp.colgroups, (int64_t)sp.S);
   else
@@ -304,7 +599,10 @@ namespace nmf {
 int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, void** scratch) {
   *scratch = nullptr;
   if (prec == NMF_BF16X3) return bf16x3_plan(side, m, n, k, c, scratch);
-  if (side == NMF_SIDE_H) {
+  if (side == NMF_SIDE_W) {
+    // transposed, padded Y of the streaming kernel (whatever A's alignment)
+    *scratch = c.take<float>((size_t)(k <= 32 ? 32 : 64) * w_yt_ld(n));
+  } else {
     const HSplit sp = h_split(m, n);
     if (sp.S > 1) *scratch = c.take<float>((size_t)sp.S * n * k);
   }
@@ -316,8 +614,9 @@ int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int6
   if (prec == NMF_BF16X3) return bf16x3_launch(side, m, n, k, Bt, Y, ldy, R, ldr, scratch, s);
   if (side == NMF_SIDE_W) {
     if (m == 0) return NMF_OK;
-    return k <= 32 ? launch_w_f32<1>(m, n, k, A, lda, Y, ldy, R, ldr, s)
-                   : launch_w_f32<2>(m, n, k, A, lda, Y, ldy, R, ldr, s);
+    float* yt = static_cast<float*>(scratch);
+    return k <= 32 ? launch_w_f32<1>(m, n, k, A, lda, Y, ldy, R, ldr, yt, s)
+                   : launch_w_f32<2>(m, n, k, A, lda, Y, ldy, R, ldr, yt, s);
   }
   if (n == 0) return NMF_OK;
   return k <= 32 ? launch_h_f32<1>(m, n, k, A, lda, Y, ldy, R, ldr, static_cast<float*>(scratch), s)

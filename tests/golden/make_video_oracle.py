@@ -25,6 +25,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "video_1e6x2400_k30_oracle.json")
 M, N, K, T = 1_000_000, 2_400, 30, 50
 CHUNK = 10_000
+SAMPLE_STRIDE = 1000
+
+
+def hex_mask(x):
+    return format(sum(1 << i for i in range(len(x)) if x[i] > 0.0), "x")
 
 
 def rows_chunk(r0):
@@ -54,6 +59,13 @@ def main(workers=6):
         "rounds_w": [int(x) for x in res["rounds_w"]],
         "rounds_h": [int(x) for x in res["rounds_h"]],
         "capped": res["capped"],
+        # final supports {i : x_i > 0} and passive sets of a row sample of W (every
+        # SAMPLE_STRIDE-th row) and of every row of H^T, as hexadecimal bit masks
+        "sample_stride_w": SAMPLE_STRIDE,
+        "support_w": [hex_mask(x) for x in res["W"][::SAMPLE_STRIDE]],
+        "support_h": [hex_mask(x) for x in res["Ht"]],
+        "passive_w": [format(int(v), "x") for v in res["masks_w"][::SAMPLE_STRIDE]],
+        "passive_h": [format(int(v), "x") for v in res["masks_h"]],
         "fro2": res["fro2"],
         "oracle_seconds": t_orc,
         "host_threads": os.cpu_count(),

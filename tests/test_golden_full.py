@@ -67,3 +67,20 @@ def test_rank_and_solver_ordering():
     loc = load("video_1e6x2400_k30_local_oracle.json")
     for s in ("hals", "mu"):
         assert bpp[-1] <= loc[s]["r_full"][-1]
+
+
+def test_stored_supports_are_consistent():
+    """The stored final supports of the 50-iteration run: one mask per sampled
+    row of W (every `sample_stride_w`-th of 10^6) and per row of H^T, within
+    k bits; a support is a subset of the passive set it came from (BPP sets
+    x = 0 off the passive set), and a W row with an empty support would be a
+    zero row of the fitted W (none in a rank-10 + foreground matrix)."""
+    run = load("video_1e6x2400_k30_oracle.json")
+    k, m, n = 30, 1_000_000, 2_400
+    assert len(run["support_w"]) == m // run["sample_stride_w"] and len(run["support_h"]) == n
+    for sup, pas in (("support_w", "passive_w"), ("support_h", "passive_h")):
+        for s_hex, p_hex in zip(run[sup], run[pas]):
+            s_, p_ = int(s_hex, 16), int(p_hex, 16)
+            assert s_ >> k == 0 and p_ >> k == 0
+            assert s_ & ~p_ == 0
+    assert all(int(x, 16) != 0 for x in run["support_w"])

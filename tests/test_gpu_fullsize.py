@@ -32,6 +32,9 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
 U32 = 2.0 ** -24
 TOL_R = 1e-5
 
@@ -203,20 +206,29 @@ def test_video_full_trajectories(video):
         rh = np.array([s["r_half"] for s in st])
         dr = max(np.max(np.abs(rf - ref["r_full"])), np.max(np.abs(rh - ref["r_half"])))
         r_direct = float(L.nmf_objective(M, W, Ht)[0])
+        agree = bench.passive_set_agreement(W, Ht, ref, k)
         print(f"{label}: max |dr| over 50 iterations {dr:.2e}; final direct r {r_direct:.10f} "
-              f"oracle {ref['r_full'][-1]:.10f}")
+              f"oracle {ref['r_full'][-1]:.10f}; support agreement W {agree['w']['agreement']:.6f} "
+              f"H {agree['h']['agreement']:.6f}")
         assert dr <= TOL_R
         assert abs(r_direct - ref["r_full"][-1]) <= TOL_R
         assert all(s["capped"] == 0 for s in st)
+        # final supports against the oracle's on every 1000th row of W and every row of H^T
+        assert agree["w"]["agreement"] >= 0.999 and agree["h"]["agreement"] >= 0.999
 
 
 def test_video_full_learned_form():
     """The bench's learned + BF16x3 configuration (5 cold iterations that
     collect samples, network training on the GPU, 45 warm-started iterations):
-    the same trajectory as the oracle, and what the trained networks save in
-    BPP rounds against cold starts over the same iterations."""
-    sys.path.insert(0, ROOT)
-    import bench
+    the same trajectory as the oracle, and what the trained networks' start
+    sets save against the trivial starts over the same 45 iterations.
+
+    Measured on this workload the W-side network predicts the full set (every
+    index passive) for every row: it needs as many passive-set solves as the
+    full-set start and saves the empty start's free first round, but the
+    previous iteration's sets need fewer solves still.  The asserts hold
+    exactly that: no more solves than the full-set start, fewer KKT rounds
+    than the empty start, and no more solves than the empty start."""
     a = bench.parse([])
     B = bench.Bench(a)
     B.learned_step()
@@ -228,16 +240,25 @@ def test_video_full_learned_form():
     r_final = B.final_r()
     assert dr <= TOL_R and abs(r_final - ref["r_full"][-1]) <= TOL_R
     assert sum(s["capped"] for s in st) == 0
-    # cold BF16x3 over the same iterations
-    _, _, cold = _run(B.M, a.k, B.W0, B.Ht0, a.iters, prec=L.NMF_BF16X3)
-    lw = sum(s["bpp_w"][0] for s in st[a.cold_iters:])
-    cw = sum(s["bpp_w"][0] for s in cold[a.cold_iters:])
-    lh = sum(s["bpp_h"][0] for s in st[a.cold_iters:])
-    ch = sum(s["bpp_h"][0] for s in cold[a.cold_iters:])
+    T0 = a.cold_iters
+
+    def tot(stats, side, c):
+        return sum(s[side][c] for s in stats[T0:])
+
+    runs = {}
+    for name, warm in (("cold", L.NMF_WARM_COLD), ("full_set", L.NMF_WARM_ALL), ("prev", L.NMF_WARM_PREV)):
+        _, _, runs[name] = _run(B.M, a.k, B.W0, B.Ht0, a.iters, prec=L.NMF_BF16X3, warm=warm)
+        assert max(abs(s["r_full"] - r) for s, r in zip(runs[name], ref["r_full"])) <= TOL_R
     fb = sum(s["fallback"] for s in st)
-    print(f"learned: max |dr| {dr:.2e}, final r {r_final:.10f}; BPP rounds in iterations "
-          f"{a.cold_iters + 1}-{a.iters}: W {lw} vs cold {cw} ({lw / cw:.3f}), H {lh} vs cold {ch}; fallbacks {fb}")
-    assert lw < cw
+    line = [f"learned W solves {tot(st, 'bpp_w', 1)} rounds {tot(st, 'bpp_w', 0)}"]
+    for name, r in runs.items():
+        line.append(f"{name} W solves {tot(r, 'bpp_w', 1)} rounds {tot(r, 'bpp_w', 0)}")
+    print(f"learned: max |dr| {dr:.2e}, final r {r_final:.10f}, fallbacks {fb}; iterations {T0 + 1}-{a.iters}: "
+          + "; ".join(line))
+    assert fb == 0
+    assert tot(st, "bpp_w", 1) <= 1.001 * tot(runs["full_set"], "bpp_w", 1)
+    assert tot(st, "bpp_w", 1) <= tot(runs["cold"], "bpp_w", 1)
+    assert tot(st, "bpp_w", 0) < tot(runs["cold"], "bpp_w", 0)
 
 
 # --------------------------------------------------- planted 172800 x 115200
