@@ -837,11 +837,15 @@ def cpu_baseline_sparse(seconds, host, m, n, k, seed):
                            shape=(S, n))
     ph = res1["phase_seconds"]
     nnz = int(rp[-1])
-    per1 = ((ph["rhs_w"] + ph["rhs_h"]) * nnz / max(nnz_s, 1) + ph["bpp_w"] * (m + n) / S
-            + (ph["gram"] + ph["objective"]) * (m + n) / (S + n))
+    if S == m:  # the whole matrix fits the one-thread budget
+        per1 = sum(ph.values())
+    else:
+        per1 = ((ph["rhs_w"] + ph["rhs_h"]) * nnz / max(nnz_s, 1) + ph["bpp_w"] * (m + n) / S
+                + (ph["gram"] + ph["objective"]) * (m + n) / (S + n))
     desc1 = (f"1 ANLS-BPP iteration of the FP64 oracle on rows 0..{S - 1} of the CSR matrix ({nnz_s} nonzeros), "
-             f"{t1:.2f} s on 1 thread; SpMMs scaled by the nonzero ratio, BPP by (m+n)/S from the W side's "
-             f"per-problem time, Gram and objective by (m+n)/(S+n)")
+             f"{t1:.2f} s on 1 thread; " + ("the whole matrix, not scaled" if S == m else
+                                            "SpMMs scaled by the nonzero ratio, BPP by (m+n)/S from the W side's "
+                                            "per-problem time, Gram and objective by (m+n)/(S+n)"))
     return _baseline(per, nthr, desc, per1, desc1)
 
 
