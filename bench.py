@@ -557,10 +557,53 @@ def local_forms(bench):
                                            "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg,
                                            "fp64_tflops": 2.0 * a.k * a.k * a.m / (ph["bpp_w"] * 1e-3) / 1e12},
                      "phase_ms_per_iter": ph}
+        if not a.no_cpu_baseline:
+            out[name]["cpu_baseline"] = cpu_baseline_local(bench, name, a.cpu_seconds / 2)
         print(f"# {name}: {out[name]['ms_per_step']:.1f} ms/step, final r {r:.8f}", file=sys.stderr, flush=True)
     out["note"] = ("the update phase is reported in the bpp_* slots of phase_ms_per_iter; "
                    "r after the same number of iterations differs between solvers (BPP solves each NNLS exactly)")
     return out
+
+
+def cpu_baseline_local(bench, solver, seconds):
+    """The FP64 oracle of Algorithm 1 with the HALS or MU update (NumPy, its
+    matrix products on the host BLAS) on the first S rows of the headline
+    matrix for one iteration, scaled by m / S (the products and the W update
+    run over the rows; the H update of 2,400 rows is a small part), at the
+    BLAS's default thread count and at one thread."""
+    import threadpoolctl
+
+    from oracle import local as olocal
+    a = bench.a
+    W0 = bench.W0.cpu().numpy()
+    H0 = bench.Ht0.cpu().numpy()
+
+    def run(S):
+        A = bench.A[:S].cpu().numpy()
+        t0 = time.perf_counter()
+        olocal.anls_trace(solver, a.k, W0[:S], H0, 1, A)
+        return time.perf_counter() - t0
+
+    def sized():
+        S = min(a.m, 20_000)
+        t = run(S)
+        S2 = int(min(a.m, max(S, S * seconds / max(t, 1e-3))))
+        if S2 > S:
+            S, t = S2, run(S2)
+        return S, t
+
+    info = threadpoolctl.threadpool_info()
+    nthr = max([d.get("num_threads", 1) for d in info] or [1])
+    S, t = sized()
+    with threadpoolctl.threadpool_limits(1):
+        S1, t1 = sized()
+    per, per1 = t * a.m / S, t1 * a.m / S1
+
+    def desc(S, t, thr):
+        return (f"1 iteration of the FP64 {solver.upper()} oracle (NumPy, host BLAS) on rows 0..{S - 1} "
+                f"({S} x {a.n}, k={a.k}), {t:.2f} s on {thr} thread(s), scaled by {a.m}/{S}")
+
+    return _baseline(per, nthr, desc(S, t, nthr), per1, desc(S1, t1, 1))
 
 
 # ------------------------------------------------------------ batched (c4) --
@@ -944,6 +987,15 @@ def ksweep_mode(a):
              ("mu_bf16x3", dict(prec=L.NMF_BF16X3, solver=L.NMF_SOLVER_MU)))
     out = {"workload": f"video-like dense {m}x{n}, {T} iterations per step from the seeded start, cold BPP",
            "ks": list(KS), "forms": {}}
+    if not a.no_cpu_baseline:
+        # the FP64 oracle's ANLS-BPP time per iteration at each k on this host (row sample, scaled)
+        import types
+        out["cpu_baseline"] = {}
+        for k in KS:
+            W0, Ht0 = gen.init_factors(seed, m, n, k)
+            fake = types.SimpleNamespace(a=types.SimpleNamespace(m=m, n=n, k=k, iters=T), A=A, W0=W0, Ht0=Ht0)
+            out["cpu_baseline"][str(k)] = cpu_baseline_video(fake, a.cpu_seconds / 2)
+            del W0, Ht0
     for name, kw in forms:
         rows = []
         for k in KS:

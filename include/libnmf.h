@@ -368,7 +368,8 @@ typedef struct nmf_batch_problem {
   int64_t ldh;
 } nmf_batch_problem;
 
-/* Work-item sizes of the grouped phases (what the autotuner chooses). */
+/* Work-item sizes and tile shapes of the grouped phases (what the autotuner
+ * chooses). */
 typedef struct nmf_batch_tune {
   int gram_tiles;    /* 64-row tiles per Gram work item (>= 1) */
   int rhs_w_chunks;  /* 64-column chunks of the contraction per A H^T item (>= 1; split-K) */
@@ -380,6 +381,11 @@ typedef struct nmf_batch_tune {
                       * warm start still unsolved after 8 rounds restarts cold);
                       * the solutions are the same either way.  Not searched by the
                       * autotuner, which keeps the default (1). */
+  int rhs_tile_rows; /* rows of R per product tile: 128 (four wavefronts) or 64 (two) */
+  int bpp_wide;      /* 0: each instance's NNLS problems in the narrowest lane class
+                      * that holds k (8, 16, 32, 56 or 64 lanes per problem); 1: the
+                      * next wider class (more lanes per problem, fewer problems per
+                      * wavefront).  Same solutions either way. */
 } nmf_batch_tune;
 
 #define NMF_BATCH_RESET 1  /* flag: clear the kept passive sets first (cold start) */
@@ -414,8 +420,9 @@ int nmf_batch_graph_create(void* plan, int iters, uint64_t* counters, int flags,
 int nmf_batch_graph_launch(void* graph, void* stream);
 int nmf_batch_graph_destroy(void* graph);
 
-/* Chooses the work-item sizes by timing one iteration per candidate
- * (coordinate search over each field in turn, starting from the default).
+/* Chooses the work-item sizes, the product tile shape and the NNLS lane
+ * classes by timing one iteration per candidate (coordinate search over each
+ * field in turn, starting from the default).
  * The problems' W and Ht are saved to the workspace first and restored
  * afterwards, so the batch is left as it was.  ws must hold
  * nmf_batch_workspace_bytes(count, P, NULL).  best_ms: time of one iteration

@@ -75,7 +75,7 @@ class nmf_batch_problem(ctypes.Structure):
 
 class nmf_batch_tune(ctypes.Structure):
     _fields_ = [("gram_tiles", ci), ("rhs_w_chunks", ci), ("rhs_h_chunks", ci), ("bpp_problems", ci),
-                ("grid_scale", ci), ("warm_prev", ci)]
+                ("grid_scale", ci), ("warm_prev", ci), ("rhs_tile_rows", ci), ("bpp_wide", ci)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

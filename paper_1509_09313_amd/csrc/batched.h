@@ -35,7 +35,7 @@ struct SplitYItem {
   int64_t ldt, K0;
 };
 
-// one 128-row tile of R = B * Y over 64-column chunks [kc0, kc1)
+// one tile (64 or 128 rows from row0) of R = B * Y over 64-column chunks [kc0, kc1)
 struct Bf16Item {
   const uint16_t* B;
   int64_t Rp, nkc;
@@ -77,7 +77,7 @@ struct BppItem {
 int gram_grouped_launch(const GramItem* items, int64_t n, int grid, hipStream_t s);
 int gram_reduce_grouped_launch(const GramReduceItem* items, int64_t n, int grid, hipStream_t s);
 int split_y_grouped_launch(const SplitYItem* items, int64_t n, int grid, hipStream_t s);
-int bf16x3_grouped_launch(int NT, const Bf16Item* items, int64_t n, int grid, hipStream_t s);
+int bf16x3_grouped_launch(int NT, int tile_rows, const Bf16Item* items, int64_t n, int grid, hipStream_t s);
 int split_reduce_grouped_launch(const SplitReduceItem* items, int64_t n, int grid, hipStream_t s);
 int bpp_grouped_launch(int K, const BppItem* items, int64_t n, int grid, int max_rounds, int warm_cap,
                        uint64_t* counters, hipStream_t s);
@@ -88,6 +88,6 @@ int bf16_grouped_occupancy(int which, int* per_cu);
 int bpp_grouped_occupancy(int K, int* per_cu);
 int bpp_class(int k);
 enum { kCapGram = 0, kCapSplitY, kCapBf16NT1, kCapBf16NT2, kCapReduce, kCapBpp16, kCapBpp32, kCapBpp56,
-       kCapBpp64, kCapBpp8, kCapCount };
+       kCapBpp64, kCapBpp8, kCapBf16NT1T64, kCapBf16NT2T64, kCapCount };
 
 }  // namespace nmf

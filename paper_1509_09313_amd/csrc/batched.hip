@@ -1,7 +1,7 @@
 // Many uneven NMF instances at once: Algorithm 1 for every instance of a
 // batch, each phase of an iteration as one persistent launch over a work
 // list that spans all instances, a graph of whole runs, and an autotuner for
-// the work-item sizes.
+// the work-item sizes, the product tile shape and the NNLS lane classes.
 //
 // An iteration is the fixed launch sequence
 //   Gram H H^T (tiles, then per-instance sums)      -> G_H
@@ -45,6 +45,8 @@ const int kCandRhsW[] = {8, 32, kNoSplit};
 const int kCandRhsH[] = {8, 32, 128};
 const int kCandBpp[] = {128, 256, 1024};
 const int kCandGrid[] = {1, 2};
+const int kCandTile[] = {64, 128};
+const int kCandWide[] = {0, 1};
 
 nmf_batch_tune finest_tune() {
   nmf_batch_tune t;
@@ -54,12 +56,23 @@ nmf_batch_tune finest_tune() {
   t.bpp_problems = kCandBpp[0];
   t.grid_scale = 1;
   t.warm_prev = 1;
+  t.rhs_tile_rows = kCandTile[0];
+  t.bpp_wide = 0;
   return t;
 }
 
 bool tune_ok(const nmf_batch_tune& t) {
   return t.gram_tiles >= 1 && t.rhs_w_chunks >= 1 && t.rhs_h_chunks >= 1 && t.bpp_problems >= 64 &&
-         t.grid_scale >= 1 && t.grid_scale <= 8 && (t.warm_prev == 0 || t.warm_prev == 1);
+         t.grid_scale >= 1 && t.grid_scale <= 8 && (t.warm_prev == 0 || t.warm_prev == 1) &&
+         (t.rhs_tile_rows == 64 || t.rhs_tile_rows == 128) && (t.bpp_wide == 0 || t.bpp_wide == 1);
+}
+
+// NNLS lane class of an instance of rank k under tuning t
+int lane_class(int k, const nmf_batch_tune& t) {
+  const int K = nmf::bpp_class(k);
+  if (!t.bpp_wide) return K;
+  const int ci = class_index(K);
+  return kClassK[ci + 1 < kClasses ? ci + 1 : ci];
 }
 
 template <class T>
@@ -112,7 +125,7 @@ int layout(int count, const nmf_batch_problem* P, const nmf_batch_tune& t, Carve
     const int k = p.k;
     const int NT = k <= 32 ? 1 : 2;
     const int KP = 32 * NT;
-    const int K = nmf::bpp_class(k);
+    const int K = lane_class(k, t);
     const int ci = class_index(K);
     double* GH = c.take<double>((size_t)k * k);
     double* GW = c.take<double>((size_t)k * k);
@@ -165,15 +178,16 @@ int layout(int count, const nmf_batch_problem* P, const nmf_batch_tune& t, Carve
     const uint16_t* Ab = static_cast<const uint16_t*>(p.A_bf16);
     const uint16_t* Atb = static_cast<const uint16_t*>(p.At_bf16);
     const int64_t Rp_w = nmf::cdiv(m, kTR) * kTR, Rp_h = nmf::cdiv(n, kTR) * kTR;
+    const int TR = t.rhs_tile_rows;
     for (int64_t s = 0; s < Sw; ++s)
-      for (int64_t r0 = 0; r0 < m; r0 += kTR) {
+      for (int64_t r0 = 0; r0 < m; r0 += TR) {
         const int64_t kc0 = s * cw, kc1 = (kc0 + cw < nkc_w ? kc0 + cw : nkc_w);
         float* out = Sw > 1 ? (pw ? pw + s * m * k : nullptr) : RW;
         plan->rw[NT - 1].host.push_back(Bf16Item{Ab, Rp_w, nkc_w, yw, yw ? yw + (size_t)KP * ldt_w : nullptr, ldt_w,
                                                  out, k, m, k, 0, r0, kc0, kc1});
       }
     for (int64_t s = 0; s < Sh; ++s)
-      for (int64_t r0 = 0; r0 < n; r0 += kTR) {
+      for (int64_t r0 = 0; r0 < n; r0 += TR) {
         const int64_t kc0 = s * ch, kc1 = (kc0 + ch < nkc_h ? kc0 + ch : nkc_h);
         float* out = Sh > 1 ? (ph ? ph + s * n * k : nullptr) : RH;
         plan->rh[NT - 1].host.push_back(Bf16Item{Atb, Rp_h, nkc_h, yh, yh ? yh + (size_t)KP * ldt_h : nullptr, ldt_h,
@@ -299,9 +313,10 @@ int plan_build(int count, const nmf_batch_problem* P, const nmf_batch_tune& t, v
   plan->grid_reduce = capacity(rc, pc) * t.grid_scale;
   rc = nmf::bf16_grouped_occupancy(nmf::kCapSplitY, &pc);
   plan->grid_split = capacity(rc, pc) * t.grid_scale;
-  rc = nmf::bf16_grouped_occupancy(nmf::kCapBf16NT1, &pc);
+  const bool t64 = t.rhs_tile_rows == 64;
+  rc = nmf::bf16_grouped_occupancy(t64 ? nmf::kCapBf16NT1T64 : nmf::kCapBf16NT1, &pc);
   plan->grid_bf16[0] = capacity(rc, pc) * t.grid_scale;
-  rc = nmf::bf16_grouped_occupancy(nmf::kCapBf16NT2, &pc);
+  rc = nmf::bf16_grouped_occupancy(t64 ? nmf::kCapBf16NT2T64 : nmf::kCapBf16NT2, &pc);
   plan->grid_bf16[1] = capacity(rc, pc) * t.grid_scale;
   for (int q = 0; q < kClasses; ++q) {
     rc = nmf::bpp_grouped_occupancy(kClassK[q], &pc);
@@ -325,7 +340,8 @@ int enqueue(const Plan& p, int iters, uint64_t* counters, int flags, hipStream_t
     NMF_TRY(nmf::gram_reduce_grouped_launch(p.ghr.dev, p.ghr.n(), grid_for(p.grid_reduce, 1, p.ghr.n()), s));
     NMF_TRY(nmf::split_y_grouped_launch(p.syw.dev, p.syw.n(), grid_for(p.grid_split, 1, p.syw.n()), s));
     for (int q = 0; q < 2; ++q)
-      NMF_TRY(nmf::bf16x3_grouped_launch(q + 1, p.rw[q].dev, p.rw[q].n(), grid_for(p.grid_bf16[q], 1, p.rw[q].n()), s));
+      NMF_TRY(nmf::bf16x3_grouped_launch(q + 1, p.tune.rhs_tile_rows, p.rw[q].dev, p.rw[q].n(),
+                                         grid_for(p.grid_bf16[q], 1, p.rw[q].n()), s));
     NMF_TRY(nmf::split_reduce_grouped_launch(p.srw.dev, p.srw.n(), grid_for(p.grid_reduce, 1, p.srw.n()), s));
     for (int q = 0; q < kClasses; ++q)
       NMF_TRY(nmf::bpp_grouped_launch(kClassK[q], p.bw[q].dev, p.bw[q].n(), grid_for(p.grid_bpp[q], 1, p.bw[q].n()),
@@ -335,7 +351,8 @@ int enqueue(const Plan& p, int iters, uint64_t* counters, int flags, hipStream_t
     NMF_TRY(nmf::gram_reduce_grouped_launch(p.gwr.dev, p.gwr.n(), grid_for(p.grid_reduce, 1, p.gwr.n()), s));
     NMF_TRY(nmf::split_y_grouped_launch(p.syh.dev, p.syh.n(), grid_for(p.grid_split, 1, p.syh.n()), s));
     for (int q = 0; q < 2; ++q)
-      NMF_TRY(nmf::bf16x3_grouped_launch(q + 1, p.rh[q].dev, p.rh[q].n(), grid_for(p.grid_bf16[q], 1, p.rh[q].n()), s));
+      NMF_TRY(nmf::bf16x3_grouped_launch(q + 1, p.tune.rhs_tile_rows, p.rh[q].dev, p.rh[q].n(),
+                                         grid_for(p.grid_bf16[q], 1, p.rh[q].n()), s));
     NMF_TRY(nmf::split_reduce_grouped_launch(p.srh.dev, p.srh.n(), grid_for(p.grid_reduce, 1, p.srh.n()), s));
     for (int q = 0; q < kClasses; ++q)
       NMF_TRY(nmf::bpp_grouped_launch(kClassK[q], p.bh[q].dev, p.bh[q].n(), grid_for(p.grid_bpp[q], 1, p.bh[q].n()),
@@ -410,6 +427,8 @@ extern "C" void nmf_batch_tune_default(nmf_batch_tune* t) {
   t->bpp_problems = 256;
   t->grid_scale = 1;
   t->warm_prev = 1;
+  t->rhs_tile_rows = 128;
+  t->bpp_wide = 0;
 }
 
 extern "C" int nmf_batch_workspace_bytes(int count, const nmf_batch_problem* P, const nmf_batch_tune* t,
@@ -420,11 +439,20 @@ extern "C" int nmf_batch_workspace_bytes(int count, const nmf_batch_problem* P, 
   if (t) {
     *bytes = bytes_for(count, P, *t);
   } else {
-    // the finest candidates bound every tuning the autotuner builds
+    // the finest candidates bound every tuning the autotuner builds, up to
+    // the 256-byte alignment of each item list (the lane-class choice moves
+    // items between the per-class lists): a 16 KiB margin covers it
     nmf_batch_tune d;
     nmf_batch_tune_default(&d);
-    const size_t a = bytes_for(count, P, finest_tune()), b = bytes_for(count, P, d);
-    *bytes = a > b ? a : b;
+    size_t mx = 0;
+    for (int wide = 0; wide < 2; ++wide) {
+      nmf_batch_tune f = finest_tune(), e = d;
+      f.bpp_wide = e.bpp_wide = wide;
+      const size_t a = bytes_for(count, P, f), b = bytes_for(count, P, e);
+      mx = a > mx ? a : mx;
+      mx = b > mx ? b : mx;
+    }
+    *bytes = mx + ((size_t)16 << 10);
   }
   return NMF_OK;
 }
@@ -515,14 +543,27 @@ extern "C" int nmf_batch_autotune(int count, const nmf_batch_problem* P, void* w
   nmf_batch_tune_default(&cur);
   double cur_ms = 0.0;
   int rc = time_tuning(count, P, cur, ws, ws_bytes, s, &cur_ms);
-  // coordinate search: each field in turn over its candidates
-  for (int field = 0; field < 5 && rc == NMF_OK; ++field) {
-    const int* cand = field == 0 ? kCandBpp : field == 1 ? kCandRhsH : field == 2 ? kCandRhsW : field == 3 ? kCandGram : kCandGrid;
-    const int nc = field == 4 ? 2 : 3;
+  // coordinate search: each field in turn over its candidates (the NNLS lane
+  // classes and the product tile shape first, then the work-item sizes)
+  struct Field {
+    const int* cand;
+    int nc;
+    int nmf_batch_tune::*slot;
+  };
+  const Field fields[] = {{kCandWide, 2, &nmf_batch_tune::bpp_wide},
+                          {kCandTile, 2, &nmf_batch_tune::rhs_tile_rows},
+                          {kCandBpp, 3, &nmf_batch_tune::bpp_problems},
+                          {kCandRhsH, 3, &nmf_batch_tune::rhs_h_chunks},
+                          {kCandRhsW, 3, &nmf_batch_tune::rhs_w_chunks},
+                          {kCandGram, 3, &nmf_batch_tune::gram_tiles},
+                          {kCandGrid, 2, &nmf_batch_tune::grid_scale}};
+  for (const Field& f : fields) {
+    if (rc != NMF_OK) break;
+    const int* cand = f.cand;
+    const int nc = f.nc;
     for (int q = 0; q < nc && rc == NMF_OK; ++q) {
       nmf_batch_tune t = cur;
-      int* slot = field == 0 ? &t.bpp_problems : field == 1 ? &t.rhs_h_chunks : field == 2 ? &t.rhs_w_chunks
-                : field == 3 ? &t.gram_tiles : &t.grid_scale;
+      int* slot = &(t.*f.slot);
       if (*slot == cand[q]) continue;
       *slot = cand[q];
       double ms = 0.0;

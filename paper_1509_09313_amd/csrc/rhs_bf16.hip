@@ -108,12 +108,14 @@ constexpr int kBTM = kTR;          // rows of B per block (4 waves x 32)
 constexpr int kBTK = kTC;          // contraction chunk (BF16 elements)
 constexpr int kBPitch = kBTK + 8;  // LDS pitch in uint16 (144 bytes: conflict-free 16-byte reads)
 
-// One 128-row tile of R = B * Y over the 64-column chunks [kc0, kc1) of the
-// contraction, written to out (ld ldp); B in the padded BF16 form (planes
-// Rp x Cp), Y as transposed BF16 planes (KP x ldt, ldt = Cp, zero past K).
-// Wave w holds D_t[i][j] = R[row0 + 32w + j][32t + i] and accumulates three
-// MFMAs per 16-wide K step (Yhi Bhi + Ylo Bhi + Yhi Blo).  Barrier-safe for
-// repeated calls from a persistent loop.
+// One tile of 32 NW rows (NW wavefronts of 64 threads: 128 rows for the
+// single-product kernels, 64 or 128 for the grouped ones) of R = B * Y over
+// the 64-column chunks [kc0, kc1) of the contraction, written to out (ld
+// ldp); B in the padded BF16 form (planes Rp x Cp), Y as transposed BF16
+// planes (KP x ldt, ldt = Cp, zero past K).  Wave w holds D_t[i][j] =
+// R[row0 + 32w + j][32t + i] and accumulates three MFMAs per 16-wide K step
+// (Yhi Bhi + Ylo Bhi + Yhi Blo).  Barrier-safe for repeated calls from a
+// persistent loop.
 typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
 
 // The planes of A are read once per launch: non-temporal loads stream them
@@ -124,13 +126,18 @@ __device__ __forceinline__ uint4 load_stream(const uint16_t* p) {
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
-template <int NT>
+template <int NT, int NW = 4>
 __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t* __restrict__ B, int64_t Rp,
                                             int64_t nkc, const uint16_t* __restrict__ Yth,
                                             const uint16_t* __restrict__ Ytl, int64_t ldt, float* __restrict__ out,
                                             int64_t ldp, int64_t row0, int64_t kc0, int64_t kc1) {
   constexpr int KP = 32 * NT;
-  __shared__ __align__(16) uint16_t Bs[2][kBTM * kBPitch];
+  constexpr int TM = 32 * NW;     // rows of the tile
+  constexpr int NTH = 64 * NW;    // threads
+  constexpr int RPP = NTH / 8;    // rows one load pass covers (8 threads per 128-byte row)
+  constexpr int YL = KP / RPP;    // load passes over each Y plane
+  static_assert(TM == 4 * RPP && YL >= 1 && YL <= 4, "tile staging layout");
+  __shared__ __align__(16) uint16_t Bs[2][TM * kBPitch];
   __shared__ __align__(16) uint16_t Ys[2][KP * kBPitch];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j = lane & 31, h = lane >> 5;
@@ -144,13 +151,13 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
   // A chunk in flight: the staging registers of one 64-column chunk (explicit
   // members: no arrays, which keeps them out of scratch).
   struct Stage {
-    uint4 bh0, bh1, bh2, bh3, bl0, bl1, bl2, bl3, yh0, yl0, yh1, yl1;
+    uint4 bh0, bh1, bh2, bh3, bl0, bl1, bl2, bl3, yh0, yl0, yh1, yl1, yh2, yl2, yh3, yl3;
   };
   auto load = [&](Stage& S, int64_t kc) __attribute__((always_inline)) {
     const int64_t c0 = kc * kTC;
     const uint16_t* ph = Bh + (int64_t)(t >> 3) * Cp + c0 + 8 * (t & 7);
     const uint16_t* pl = ph + Rp * Cp;
-    const int64_t rs = 32 * Cp;  // 256 threads cover 32 rows
+    const int64_t rs = RPP * Cp;
     S.bh0 = load_stream(ph);
     S.bh1 = load_stream(ph + rs);
     S.bh2 = load_stream(ph + 2 * rs);
@@ -162,26 +169,38 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
     const int64_t yo = (int64_t)(t >> 3) * ldt + c0 + 8 * (t & 7);
     S.yh0 = *reinterpret_cast<const uint4*>(Yth + yo);
     S.yl0 = *reinterpret_cast<const uint4*>(Ytl + yo);
-    if (NT == 2) {
-      S.yh1 = *reinterpret_cast<const uint4*>(Yth + yo + 32 * ldt);
-      S.yl1 = *reinterpret_cast<const uint4*>(Ytl + yo + 32 * ldt);
+    if (YL > 1) {
+      S.yh1 = *reinterpret_cast<const uint4*>(Yth + yo + RPP * ldt);
+      S.yl1 = *reinterpret_cast<const uint4*>(Ytl + yo + RPP * ldt);
+    }
+    if (YL > 2) {
+      S.yh2 = *reinterpret_cast<const uint4*>(Yth + yo + 2 * RPP * ldt);
+      S.yl2 = *reinterpret_cast<const uint4*>(Ytl + yo + 2 * RPP * ldt);
+      S.yh3 = *reinterpret_cast<const uint4*>(Yth + yo + 3 * RPP * ldt);
+      S.yl3 = *reinterpret_cast<const uint4*>(Ytl + yo + 3 * RPP * ldt);
     }
   };
   const int so = (t >> 3) * kBPitch + 8 * (t & 7);
   auto store = [&](const Stage& S) __attribute__((always_inline)) {
     *reinterpret_cast<uint4*>(&Bs[0][so]) = S.bh0;
-    *reinterpret_cast<uint4*>(&Bs[0][so + 32 * kBPitch]) = S.bh1;
-    *reinterpret_cast<uint4*>(&Bs[0][so + 64 * kBPitch]) = S.bh2;
-    *reinterpret_cast<uint4*>(&Bs[0][so + 96 * kBPitch]) = S.bh3;
+    *reinterpret_cast<uint4*>(&Bs[0][so + RPP * kBPitch]) = S.bh1;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 2 * RPP * kBPitch]) = S.bh2;
+    *reinterpret_cast<uint4*>(&Bs[0][so + 3 * RPP * kBPitch]) = S.bh3;
     *reinterpret_cast<uint4*>(&Bs[1][so]) = S.bl0;
-    *reinterpret_cast<uint4*>(&Bs[1][so + 32 * kBPitch]) = S.bl1;
-    *reinterpret_cast<uint4*>(&Bs[1][so + 64 * kBPitch]) = S.bl2;
-    *reinterpret_cast<uint4*>(&Bs[1][so + 96 * kBPitch]) = S.bl3;
+    *reinterpret_cast<uint4*>(&Bs[1][so + RPP * kBPitch]) = S.bl1;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 2 * RPP * kBPitch]) = S.bl2;
+    *reinterpret_cast<uint4*>(&Bs[1][so + 3 * RPP * kBPitch]) = S.bl3;
     *reinterpret_cast<uint4*>(&Ys[0][so]) = S.yh0;
     *reinterpret_cast<uint4*>(&Ys[1][so]) = S.yl0;
-    if (NT == 2) {
-      *reinterpret_cast<uint4*>(&Ys[0][so + 32 * kBPitch]) = S.yh1;
-      *reinterpret_cast<uint4*>(&Ys[1][so + 32 * kBPitch]) = S.yl1;
+    if (YL > 1) {
+      *reinterpret_cast<uint4*>(&Ys[0][so + RPP * kBPitch]) = S.yh1;
+      *reinterpret_cast<uint4*>(&Ys[1][so + RPP * kBPitch]) = S.yl1;
+    }
+    if (YL > 2) {
+      *reinterpret_cast<uint4*>(&Ys[0][so + 2 * RPP * kBPitch]) = S.yh2;
+      *reinterpret_cast<uint4*>(&Ys[1][so + 2 * RPP * kBPitch]) = S.yl2;
+      *reinterpret_cast<uint4*>(&Ys[0][so + 3 * RPP * kBPitch]) = S.yh3;
+      *reinterpret_cast<uint4*>(&Ys[1][so + 3 * RPP * kBPitch]) = S.yl3;
     }
   };
   auto compute = [&]() __attribute__((always_inline)) {
@@ -200,7 +219,9 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
       }
     }
   };
-  if (kc1 - kc0 >= 4) {
+  // the 64-row form keeps one chunk in flight (two staging sets take it past
+  // 256 VGPRs)
+  if (NW == 4 && kc1 - kc0 >= 4) {
     // Two chunks in flight: the loads of chunk c + 2 are issued while chunk
     // c + 1 is still arriving.  The main loop's loads are unconditional, so
     // each wait is for the older set only; the last two or three chunks
@@ -256,7 +277,7 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
   // stream more (10^6 x 2400, k = 30: 1.715 ms scattered, 1.688 through LDS,
   // 1.620 through LDS non-temporal; 1.417 with no output at all).
   constexpr int OP = KP + 1;  // odd pitch: conflict-free column writes
-  static_assert(kBTM * OP * sizeof(float) <= sizeof(Bs), "output tile exceeds the staging buffer");
+  static_assert(TM * OP * sizeof(float) <= sizeof(Bs), "output tile exceeds the staging buffer");
   float* O = reinterpret_cast<float*>(&Bs[0][0]);
   __syncthreads();
 #pragma unroll
@@ -264,8 +285,8 @@ __device__ __forceinline__ void bf16x3_tile(int64_t rows, int k, const uint16_t*
 #pragma unroll
     for (int v = 0; v < 16; ++v) O[(32 * w + j) * OP + 32 * tt + (v & 3) + 8 * (v >> 2) + 4 * h] = acc[tt][v];
   __syncthreads();
-  const int nr = rows - row0 < kBTM ? (int)(rows - row0) : kBTM;
-  for (int e = t; e < nr * k; e += 256) {
+  const int nr = rows - row0 < TM ? (int)(rows - row0) : TM;
+  for (int e = t; e < nr * k; e += NTH) {
     const int row = e / k, c = e - row * k;
     __builtin_nontemporal_store(O[row * OP + c], &out[(row0 + row) * ldp + c]);
   }
@@ -298,13 +319,25 @@ __global__ __launch_bounds__(256) void k_rhs_bf16x3(int64_t rows, int k, const u
   bf16x3_tile<NT>(rows, k, B, Rp, nkc, Yth, Ytl, ldt, P + by * split_stride, ldp, bx * kBTM, kc0, kc1);
 }
 
-// Grouped form: a persistent walk over tiles of many products.
+// Grouped form: a persistent walk over tiles of many products, 128 rows per
+// tile (four wavefronts) ...
 template <int NT>
 __global__ __launch_bounds__(256) void k_rhs_bf16x3_grouped(const nmf::Bf16Item* __restrict__ items, int64_t n) {
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     const nmf::Bf16Item it = items[i];
-    bf16x3_tile<NT>(it.rows, it.k, it.B, it.Rp, it.nkc, it.Yth, it.Ytl, it.ldt, it.out, it.ldp, it.row0, it.kc0,
-                    it.kc1);
+    bf16x3_tile<NT, 4>(it.rows, it.k, it.B, it.Rp, it.nkc, it.Yth, it.Ytl, it.ldt, it.out, it.ldp, it.row0, it.kc0,
+                       it.kc1);
+  }
+}
+
+// ... or 64 rows (two wavefronts, one chunk in flight).
+template <int NT>
+__global__ __launch_bounds__(128) void k_rhs_bf16x3_grouped64(
+    const nmf::Bf16Item* __restrict__ items, int64_t n) {
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::Bf16Item it = items[i];
+    bf16x3_tile<NT, 2>(it.rows, it.k, it.B, it.Rp, it.nkc, it.Yth, it.Ytl, it.ldt, it.out, it.ldp, it.row0, it.kc0,
+                       it.kc1);
   }
 }
 
@@ -486,12 +519,19 @@ int split_y_grouped_launch(const SplitYItem* items, int64_t n, int grid, hipStre
   return launch_status("split Y (grouped)");
 }
 
-int bf16x3_grouped_launch(int NT, const Bf16Item* items, int64_t n, int grid, hipStream_t s) {
+int bf16x3_grouped_launch(int NT, int tile_rows, const Bf16Item* items, int64_t n, int grid, hipStream_t s) {
   if (n == 0) return NMF_OK;
-  if (NT == 1)
-    hipLaunchKernelGGL(k_rhs_bf16x3_grouped<1>, dim3((unsigned)grid), dim3(256), 0, s, items, n);
-  else
-    hipLaunchKernelGGL(k_rhs_bf16x3_grouped<2>, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+  if (tile_rows == 64) {
+    if (NT == 1)
+      hipLaunchKernelGGL(k_rhs_bf16x3_grouped64<1>, dim3((unsigned)grid), dim3(128), 0, s, items, n);
+    else
+      hipLaunchKernelGGL(k_rhs_bf16x3_grouped64<2>, dim3((unsigned)grid), dim3(128), 0, s, items, n);
+  } else {
+    if (NT == 1)
+      hipLaunchKernelGGL(k_rhs_bf16x3_grouped<1>, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+    else
+      hipLaunchKernelGGL(k_rhs_bf16x3_grouped<2>, dim3((unsigned)grid), dim3(256), 0, s, items, n);
+  }
   return launch_status("rhs bf16x3 (grouped)");
 }
 
@@ -508,6 +548,10 @@ int bf16_grouped_occupancy(int which, int* per_cu) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_rhs_bf16x3_grouped<1>, 256, 0);
   if (which == kCapBf16NT2)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_rhs_bf16x3_grouped<2>, 256, 0);
+  if (which == kCapBf16NT1T64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_rhs_bf16x3_grouped64<1>, 128, 0);
+  if (which == kCapBf16NT2T64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_rhs_bf16x3_grouped64<2>, 128, 0);
   if (which == kCapReduce)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_reduce_splits_grouped, 256, 0);
   return e == hipSuccess ? NMF_OK : NMF_EHIP;

@@ -102,7 +102,7 @@ def test_struct_layouts_match_header(L):
     assert ctypes.sizeof(L.nmf_iter_stats) == 8 * (2 + 2 * L.NMF_BPP_COUNTERS + 2)
     assert L.nmf_matrix.fro2.offset == ctypes.sizeof(L.nmf_matrix) - 8
     assert ctypes.sizeof(L.nmf_batch_problem) == 8 * 2 + 4 * 2 + 8 * 6
-    assert ctypes.sizeof(L.nmf_batch_tune) == 4 * 6
+    assert ctypes.sizeof(L.nmf_batch_tune) == 4 * 8
 
 
 def test_batch_host_validation_without_gpu(L):

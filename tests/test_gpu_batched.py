@@ -166,3 +166,38 @@ def test_batched_warm_prev_same_solutions_fewer_rounds():
     print(f"cold vs previous-set starts: max |dr| {dr:.2e}; BPP rounds {rounds0} -> {rounds1}")
     assert dr <= 1e-7
     assert rounds1 < rounds0
+
+
+@pytest.mark.parametrize("tile_rows,wide", [(64, 0), (128, 1), (64, 1)])
+def test_batched_tile_shapes_and_lane_classes_vs_oracle(tile_rows, wide):
+    """The tile shapes and lane classes the autotuner chooses between: 64-row
+    product tiles give right-hand sides bit-identical to the 128-row tiles
+    (the same MFMA chain per output entry), and the wider NNLS lane classes
+    the same unique solutions; every instance stays within 1e-5 of the oracle
+    after 3 iterations."""
+    seed = C.seed_for(4) + 5000
+    T = 3
+    probs, shapes = build(SMALL, seed)
+    refs = []
+    for i, (m, n, k) in enumerate(shapes):
+        A = C.planted_dense(seed, m, n, k, 0.01, inst=i)
+        refs.append(oracle.anls(k, C.init_w(seed, m, k, inst=i), C.init_ht(seed, n, k, inst=i), T, dense=A))
+    out = {}
+    for label, (tr, wd) in (("default", (128, 0)), ("chosen", (tile_rows, wide))):
+        for pr, (m, n, k), i in zip(probs, shapes, range(len(shapes))):
+            W, Ht = gen.init_factors(seed, m, n, k, inst=i)
+            pr["W"].copy_(W)
+            pr["Ht"].copy_(Ht)
+        t = L.batch_tune_default()
+        t.rhs_tile_rows, t.bpp_wide = tr, wd
+        b = L.Batch(probs, tune=t)
+        b.iterate(T, reset=True)
+        torch.cuda.synchronize()
+        out[label] = [(pr["W"].clone(), pr["Ht"].clone(), direct_r(pr)) for pr in probs]
+        b.close()
+    for i, ((Wd, Hd, rd), (Wc, Hc, rc)) in enumerate(zip(out["default"], out["chosen"])):
+        assert abs(rc - refs[i]["r_full"][-1]) <= TOL_R, (i, shapes[i], rc, refs[i]["r_full"][-1])
+        if wide == 0:
+            assert torch.equal(Wd, Wc) and torch.equal(Hd, Hc), (i, shapes[i])
+        else:
+            assert abs(rc - rd) <= 1e-7, (i, shapes[i], rc, rd)
