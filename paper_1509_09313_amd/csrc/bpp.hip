@@ -22,7 +22,9 @@
 //     x_p = rhs_p / pivot_p   (p in F)      y_p = -rhs_p   (p not in F)
 // gives the primal solution and the dual y = G x - f without another pass.
 // The infeasible set V = {p in F: x_p < 0} U {p not in F: y_p < 0} is a
-// ballot; the exchange rule is evaluated identically by every lane.
+// ballot; the exchange rule is evaluated identically by every lane.  In the
+// one-problem classes the pivot columns are first packed at the end of the
+// row (see the elimination), so a step touches only later pivots.
 //
 // Two forms of the same passive-set solve.  Each block also sweeps G once
 // (symmetric sweep operator over the unpinned indices U, FP64, index order)
@@ -65,8 +67,12 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
   __shared__ double Gs[K * K];
   __shared__ double Gi[K * K];
   __shared__ int inv_ok_s;
-  __shared__ double colv[kWaves][64];
-  __shared__ double rfv[kWaves][64];
+  // one slot per lane, plus (one-problem classes) a spare slot 64 for the
+  // packed form's non-pivot lanes
+  constexpr int kSlots = P == 1 ? 65 : 64;
+  __shared__ double colv[kWaves][kSlots];
+  __shared__ double rfv[kWaves][kSlots];
+  __shared__ double dgv[kWaves][P == 1 ? 65 : 1];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool lane_in = lane < P * K;
@@ -312,6 +318,82 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
           x = inF ? own : 0.0;
           y = inF ? 0.0 : corr - f;
         }
+      } else if constexpr (P == 1) {
+        // One problem per wavefront, so the pivot set is uniform.  The n_p
+        // pivots are packed, in index order, at the end of a K-wide register
+        // row (pivot c at position K - n_p + c): each step then updates only
+        // the positions of the later pivots, about n_p^2 / 2 updates per
+        // round instead of n_p K / 2, and the non-pivot columns are never
+        // gathered.  A pivot lane publishes its entries at its own packed
+        // slot, so every read of a step has a compile-time offset.  The
+        // arithmetic on the pivot columns, and its order, is that of the
+        // unpacked elimination below.
+        const int np = __popcll(Pv);
+        const int off = K - np;
+        const bool inP = (Pv >> p) & 1ull;
+        const int slot = inP ? off + __popcll(Pv & (bit64(p) - 1ull)) : 64;
+        double* colw = &colv[wave][0];
+        double* rfw = &rfv[wave][0];
+        double* dgw = &dgv[wave][0];
+        double r[K];
+        {
+          uint64_t rem = Pv;
+#pragma unroll
+          for (int c = 0; c < K; ++c) {
+            // positions before the pivots are never read; they load row 0
+            const bool real = c >= off;
+            const int jc = real ? __ffsll((unsigned long long)rem) - 1 : 0;
+            rem = real ? (rem & (rem - 1ull)) : rem;
+            r[c] = Mrow[jc * K + p];
+          }
+        }
+        dgw[slot] = Mrow[p * K + p];
+        double rf = rf0, mypiv = 1.0;
+        {
+          uint64_t rem = Pv;
+#pragma unroll
+          for (int c = 0; c < K; ++c) {
+            if (c < off) continue;
+            const int j = __ffsll((unsigned long long)rem) - 1;
+            rem &= rem - 1ull;
+            colw[slot] = r[c];
+            rfw[slot] = rf;
+            wave_lds_sync();
+            const double piv = colw[c];
+            const double zj = rfw[c];
+            bool use = true;
+            if (!(piv > 1e-12 * dgw[c])) {
+              use = false;
+              if (useInv) {
+                retry = true;
+              } else {
+                F &= ~bit64(j);
+                Fe &= ~bit64(j);
+                pinned |= bit64(j);
+                st |= NMF_BPP_SINGULAR;
+              }
+            }
+            double inv = __builtin_amdgcn_rcp(piv);
+            inv = fma(inv, fma(-piv, inv, 1.0), inv);
+            inv = fma(inv, fma(-piv, inv, 1.0), inv);
+            inv = use ? inv : 0.0;
+            const double mlt = (use && p != j) ? r[c] * inv : 0.0;
+            if (use && p == j) mypiv = piv;
+#pragma unroll
+            for (int q = c + 1; q < K; ++q) r[q] -= mlt * colw[q];
+            rf -= mlt * zj;
+            wave_lds_sync();
+          }
+        }
+        const bool inF = (Fe >> p) & 1ull;
+        const bool isPinned = (pinned >> p) & 1ull;
+        if (useInv) {
+          x = inF ? rf : 0.0;
+          y = (inF || isPinned) ? 0.0 : -rf / mypiv;
+        } else {
+          x = inF ? rf / mypiv : 0.0;
+          y = inF ? 0.0 : -rf;
+        }
       } else {
         double r[K];
 #pragma unroll
@@ -481,7 +563,7 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
 // one Gram matrix (start sets from, and final sets to, the item's masks when
 // it has them; cold starts otherwise).
 template <int K>
-__global__ __launch_bounds__(256) void k_bpp_grouped(const nmf::BppItem* __restrict__ items, int64_t n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 56 ? 2 : 1))) void k_bpp_grouped(const nmf::BppItem* __restrict__ items, int64_t n,
                                                      int max_rounds, int warm_cap,
                                                      unsigned long long* __restrict__ counters) {
   unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
