@@ -30,9 +30,21 @@ HIP_FLAGS = [
 ]
 
 
+# additions for single sources
+FILE_FLAGS = {
+    # the network inference applies its ReLU to every MFMA result: accumulators held in VGPRs
+    # spare one copy out of the accumulation registers per value
+    "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
+def flags_for(src: str) -> list[str]:
+    return HIP_FLAGS + FILE_FLAGS.get(os.path.basename(src), [])
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *HIP_FLAGS, "-c", src, "-o", obj]
+    cmd = ["hipcc", *flags_for(src), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")

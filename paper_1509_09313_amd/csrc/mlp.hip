@@ -346,9 +346,23 @@ __device__ __forceinline__ v4f mfma16(v8bf a, v8bf b, v4f c) {
 
 union Pack8 {
   uint16_t h[8];
+  uint32_t u[4];
   v8bf v;
   uint4 q;
 };
+
+// (a, b) rounded to BF16 (nearest even) in one packed conversion; a in the low half
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+// max(x, 0) as one integer max on the bit pattern (every negative float,
+// -0 included, has a negative pattern); fmaxf of an MFMA result would first
+// quieten a possible signalling NaN, a second instruction
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
 
 // 16 x 16 MFMA output layout: lane (j, g) = (lane & 15, lane >> 4) holds rows
 // 4g + v (v = 0..3) of column j.  A layer's accumulators are re-used as the
@@ -463,89 +477,102 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int k, int64_t batch, const d
         rv[s][e] = (okb && in < k) ? R[bb * ldr + in] : 0.0f;
       }
   };
+  // per-lane constants: the scale and offset of each feature slot (slot
+  // (s, e) of lane group g is input 32s + 8g + e), and the biases of the
+  // output rows the lane holds (row 16t + 4g + v of tile t), which start the
+  // accumulation of each layer
+  float sc[KS1][8], ad[KS1][8];
+#pragma unroll
+  for (int s = 0; s < KS1; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int in = 32 * s + 8 * g + e;
+      sc[s][e] = in < k ? isd[in] : 0.0f;
+      ad[s][e] = (in >= k && in < L.in) ? gft[in - k] : 0.0f;
+    }
+  v4f b1v[8], b2v[8], b3v[NT3];
+#pragma unroll
+  for (int to = 0; to < 8; ++to)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      b1v[to][v] = bias1[16 * to + 4 * g + v];
+      b2v[to][v] = bias2[16 * to + 4 * g + v];
+    }
+#pragma unroll
+  for (int to = 0; to < NT3; ++to)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b3v[to][v] = bias3[16 * to + 4 * g + v];
+
   load_rhs(tile);
   for (; tile < ntiles; tile += tstride) {
     const int64_t b = tile * 16 + j;
     const bool ok = b < batch;
-    // features of problem b: slot (s, e) of lane group g <-> input 32s + 8g + e
-    float fv[KS1][8];
+    // scaled right-hand side f_i / sqrt(G_ii) of problem b (zero past k)
+    float tv[KS1][8];
     float ss = 0.0f;
 #pragma unroll
     for (int s = 0; s < KS1; ++s)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int in = 32 * s + 8 * g + e;
-        float v = 0.0f;
-        if (in < k) {
-          v = rv[s][e] * isd[in];
-          ss += v * v;
-        } else if (in < L.in) {
-          v = gft[in - k];
-        }
-        fv[s][e] = v;
+        const float v = rv[s][e] * sc[s][e];
+        ss = fmaf(v, v, ss);
+        tv[s][e] = v;
       }
     load_rhs(tile + tstride);
     __builtin_amdgcn_sched_barrier(0);
     ss += __shfl_xor(ss, 16, 64);
     ss += __shfl_xor(ss, 32, 64);
     const float inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;
-    // layer 1
+    // layer 1 (features: the normalised scaled right-hand side, then the
+    // diagonal ratios)
     v4f a1[8];
-#pragma unroll
-    for (int to = 0; to < 8; ++to) a1[to] = v4f{};
 #pragma unroll
     for (int s = 0; s < KS1; ++s) {
       Pack8 bx;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int in = 32 * s + 8 * g + e;
-        bx.h[e] = to_bf16(in < k ? fv[s][e] * inv : fv[s][e]);
-      }
+      for (int e = 0; e < 4; ++e)
+        bx.u[e] = pk_bf16(fmaf(tv[s][2 * e], inv, ad[s][2 * e]), fmaf(tv[s][2 * e + 1], inv, ad[s][2 * e + 1]));
 #pragma unroll
       for (int to = 0; to < 8; ++to) {
         Pack8 wa;
         wa.q = *reinterpret_cast<const uint4*>(&w1s[(((to * KS1 + s) * 16 + j) * 4 + g) * 8]);
-        a1[to] = mfma16(wa.v, bx.v, a1[to]);
+        a1[to] = mfma16(wa.v, bx.v, s == 0 ? b1v[to] : a1[to]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
     // layer 2
     v4f a2[8];
 #pragma unroll
-    for (int to = 0; to < 8; ++to) a2[to] = v4f{};
-#pragma unroll
     for (int s = 0; s < 4; ++s) {
       Pack8 bx;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int ti = 2 * s + (e >> 2), v = e & 3;
-        bx.h[e] = to_bf16(fmaxf(a1[ti][v] + bias1[16 * ti + 4 * g + v], 0.0f));
+      for (int e = 0; e < 4; ++e) {
+        const int ti = 2 * s + (e >> 1), v = 2 * (e & 1);
+        bx.u[e] = pk_bf16(relu(a1[ti][v]), relu(a1[ti][v + 1]));
       }
 #pragma unroll
       for (int to = 0; to < 8; ++to) {
         Pack8 wa;
         wa.q = *reinterpret_cast<const uint4*>(&w2s[(((to * 4 + s) * 16 + j) * 4 + g) * 8]);
-        a2[to] = mfma16(wa.v, bx.v, a2[to]);
+        a2[to] = mfma16(wa.v, bx.v, s == 0 ? b2v[to] : a2[to]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
     // layer 3
     v4f a3[NT3];
 #pragma unroll
-    for (int to = 0; to < NT3; ++to) a3[to] = v4f{};
-#pragma unroll
     for (int s = 0; s < 4; ++s) {
       Pack8 bx;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int ti = 2 * s + (e >> 2), v = e & 3;
-        bx.h[e] = to_bf16(fmaxf(a2[ti][v] + bias2[16 * ti + 4 * g + v], 0.0f));
+      for (int e = 0; e < 4; ++e) {
+        const int ti = 2 * s + (e >> 1), v = 2 * (e & 1);
+        bx.u[e] = pk_bf16(relu(a2[ti][v]), relu(a2[ti][v + 1]));
       }
 #pragma unroll
       for (int to = 0; to < NT3; ++to) {
         Pack8 wa;
         wa.q = *reinterpret_cast<const uint4*>(&w3s[(((to * 4 + s) * 16 + j) * 4 + g) * 8]);
-        a3[to] = mfma16(wa.v, bx.v, a3[to]);
+        a3[to] = mfma16(wa.v, bx.v, s == 0 ? b3v[to] : a3[to]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -555,7 +582,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int k, int64_t batch, const d
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * to + 4 * g + v;
-        if (c < k && a3[to][v] + bias3[c] > 0.0f) bits |= 1ull << c;
+        if (c < k && a3[to][v] > 0.0f) bits |= 1ull << c;
       }
     bits |= __shfl_xor(bits, 16, 64);
     bits |= __shfl_xor(bits, 32, 64);

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc is 
 
 
 def kernel_resources(src):
-    cmd = ["hipcc", *B.HIP_FLAGS, "--cuda-device-only", "-c", src, "-o", os.devnull,
+    cmd = ["hipcc", *B.flags_for(src), "--cuda-device-only", "-c", src, "-o", os.devnull,
            "-Rpass-analysis=kernel-resource-usage"]
     out = subprocess.run(cmd, capture_output=True, text=True)
     assert out.returncode == 0, out.stderr[-2000:]
