@@ -11,6 +11,8 @@ namespace nmf {
 int trace_objective_launch(int64_t len, const float* a, const float* b, int k, const double* GW, const double* GH,
                            const double* fro2, double* partial, int nblocks, double* out, double* r_copy,
                            hipStream_t s);
+int trace_finish_launch(int nblocks, const double* partial, int k, const double* GW, const double* GH,
+                        const double* fro2, double* out, double* r_copy, hipStream_t s);
 // warm-start network (mlp.hip)
 int mlp_infer_plan(int k, int64_t batch, Carver& c, void** scratch);
 int mlp_pack_launch(int k, const float* params, void* scratch, hipStream_t s);
@@ -41,31 +43,6 @@ int fill_full_sets(uint64_t* masks, int64_t n, int k, hipStream_t s) {
   return nmf::launch_status("full start sets");
 }
 
-__global__ void k_status_count(int64_t n, const uint8_t* __restrict__ status, unsigned long long* __restrict__ capped,
-                               unsigned long long* __restrict__ fallback) {
-  __shared__ unsigned long long s[2][256];
-  unsigned long long c = 0, f = 0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint8_t st = status[e];
-    c += (st & NMF_BPP_CAPPED) ? 1 : 0;
-    f += (st & NMF_BPP_WARM_FALLBACK) ? 1 : 0;
-  }
-  s[0][threadIdx.x] = c;
-  s[1][threadIdx.x] = f;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      s[0][threadIdx.x] += s[0][threadIdx.x + off];
-      s[1][threadIdx.x] += s[1][threadIdx.x + off];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (s[0][0]) atomicAdd(capped, s[0][0]);
-    if (s[1][0]) atomicAdd(fallback, s[1][0]);
-  }
-}
-
 // Copies the sampled problems' final passive sets (b % stride == 0) to
 // positions base + b / stride of the sample buffer.
 __global__ void k_collect_masks(int64_t batch, int64_t stride, const uint64_t* __restrict__ masks,
@@ -91,6 +68,7 @@ struct Plan {
   double* obj;
   double* dpart;
   int dblocks;
+  double* bdot;  // per-block cross terms from the BPP kernel
   void* infer_w;
   void* infer_h;
 };
@@ -116,6 +94,10 @@ int plan_anls(const nmf_matrix* A, int k, const nmf_opts* o, nmf::Carver& c, Pla
   }
   P->obj = c.take<double>(4);
   nmf::dot_plan(mx * k, c, &P->dpart, &P->dblocks);
+  {
+    const int64_t bw = nmf::bpp_blocks(k, m), bh = nmf::bpp_blocks(k, n);
+    P->bdot = c.take<double>((size_t)(bw > bh ? (bw > 1 ? bw : 1) : (bh > 1 ? bh : 1)));
+  }
   P->infer_w = P->infer_h = nullptr;
   if (o->warm == NMF_WARM_LEARNED) {
     NMF_TRY(nmf::mlp_infer_plan(k, mx, c, &P->infer_w));
@@ -170,15 +152,6 @@ int rhs(const nmf_matrix* A, int side, int k, int prec, const float* Y, float* R
   }
   const void* bt = side == NMF_SIDE_W ? A->A_bf16 : A->At_bf16;
   return nmf::rhs_dense_launch(side, A->m, A->n, k, A->A, A->lda, bt, Y, k, R, k, prec, scratch, s);
-}
-
-int count_status(int64_t n, const uint8_t* status, nmf_iter_stats* st, hipStream_t s) {
-  int64_t blocks = nmf::cdiv(n, 256);
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_status_count, dim3((unsigned)blocks), dim3(256), 0, s, n, status,
-                     reinterpret_cast<unsigned long long*>(&st->capped),
-                     reinterpret_cast<unsigned long long*>(&st->fallback));
-  return nmf::launch_status("status count");
 }
 
 int collect(int k, int64_t batch, int64_t stride, const double* G, const float* R, const uint64_t* masks,
@@ -272,21 +245,28 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     if (o->warm == NMF_WARM_ALL) NMF_TRY(fill_full_sets(P.MW, m, k, s));
     rec(ev(t, NMF_PH_INFER_W, 1));
     rec(ev(t, NMF_PH_BPP_W, 0));
-    if (o->solver == NMF_SOLVER_BPP) {
+    // with BPP the cross term <R_W, W> of the trace objective and the status
+    // counts come out of the solve itself
+    const bool bpp = o->solver == NMF_SOLVER_BPP;
+    const bool trace = st && o->trace_objective;
+    if (bpp) {
       NMF_TRY(nmf::bpp_launch(k, m, P.GH, P.RW, k, W, k, warm ? P.MW : nullptr, P.MW, nullptr, P.status,
-                              o->max_rounds, o->warm_cap, st ? st->bpp_w : nullptr, s));
+                              o->max_rounds, o->warm_cap, st ? st->bpp_w : nullptr, s, trace ? P.bdot : nullptr,
+                              st ? &st->capped : nullptr));
     } else {
       NMF_TRY(nmf::local_update_launch(o->solver, k, m, P.GH, P.RW, k, W, k, s));
     }
     rec(ev(t, NMF_PH_BPP_W, 1));
-    if (st && o->solver == NMF_SOLVER_BPP) NMF_TRY(count_status(m, P.status, st, s));
     if (o->collect)
       NMF_TRY(collect(k, m, o->collect_stride_w, P.GH, P.RW, P.MW, o->coll_phi_w, o->coll_mask_w, o->coll_cap_w,
                       &hc[0], s));
     rec(ev(t, NMF_PH_GRAM_W, 0));
     NMF_TRY(nmf::gram_launch(m, k, W, k, P.GW, P.gpart, P.gblocks, s));
     rec(ev(t, NMF_PH_GRAM_W, 1));
-    if (st && o->trace_objective) {
+    if (trace && bpp) {
+      NMF_TRY(nmf::trace_finish_launch((int)nmf::bpp_blocks(k, m), P.bdot, k, P.GW, P.GH, A->fro2, P.obj,
+                                       &st->r_half, s));
+    } else if (trace) {
       NMF_TRY(nmf::trace_objective_launch(m * k, P.RW, W, k, P.GW, P.GH, A->fro2, P.dpart, P.dblocks, P.obj,
                                           &st->r_half, s));
     }
@@ -301,14 +281,14 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     if (o->warm == NMF_WARM_ALL) NMF_TRY(fill_full_sets(P.MH, n, k, s));
     rec(ev(t, NMF_PH_INFER_H, 1));
     rec(ev(t, NMF_PH_BPP_H, 0));
-    if (o->solver == NMF_SOLVER_BPP) {
+    if (bpp) {
       NMF_TRY(nmf::bpp_launch(k, n, P.GW, P.RH, k, Ht, k, warm ? P.MH : nullptr, P.MH, nullptr, P.status,
-                              o->max_rounds, o->warm_cap, st ? st->bpp_h : nullptr, s));
+                              o->max_rounds, o->warm_cap, st ? st->bpp_h : nullptr, s, trace ? P.bdot : nullptr,
+                              st ? &st->capped : nullptr));
     } else {
       NMF_TRY(nmf::local_update_launch(o->solver, k, n, P.GW, P.RH, k, Ht, k, s));
     }
     rec(ev(t, NMF_PH_BPP_H, 1));
-    if (st && o->solver == NMF_SOLVER_BPP) NMF_TRY(count_status(n, P.status, st, s));
     if (o->collect)
       NMF_TRY(collect(k, n, o->collect_stride_h, P.GW, P.RH, P.MH, o->coll_phi_h, o->coll_mask_h, o->coll_cap_h,
                       &hc[1], s));
@@ -316,7 +296,10 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     NMF_TRY(nmf::gram_launch(n, k, Ht, k, P.GH, P.gpart, P.gblocks, s));
     rec(ev(t, NMF_PH_GRAM_H, 1));
     rec(ev(t, NMF_PH_OTHER, 0));
-    if (st && o->trace_objective) {
+    if (trace && bpp) {
+      NMF_TRY(nmf::trace_finish_launch((int)nmf::bpp_blocks(k, n), P.bdot, k, P.GW, P.GH, A->fro2, P.obj,
+                                       &st->r_full, s));
+    } else if (trace) {
       NMF_TRY(nmf::trace_objective_launch(n * k, P.RH, Ht, k, P.GW, P.GH, A->fro2, P.dpart, P.dblocks, P.obj,
                                           &st->r_full, s));
     }

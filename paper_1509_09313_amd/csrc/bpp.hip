@@ -51,6 +51,15 @@ constexpr int kSmall = 4;  // pivot-set size handled by the small-system path
 
 __device__ __forceinline__ uint64_t bit64(int i) { return 1ull << i; }
 
+// Per-lane sums a caller may want from the solutions without reading them
+// again: sum over solved entries of f_i x_i (x rounded to FP32 as stored;
+// the cross term of the trace-form objective), and the problems that ended
+// capped or fell back from their start set.
+struct BppExtras {
+  double dot = 0.0;
+  unsigned long long capped = 0, fallback = 0;
+};
+
 // Solves problems b0 + g * P + sub (g = g_first, g_first + g_step, ... while
 // b0 + g * P < b1) of one Gram matrix G; P = 64 / K problems per wavefront,
 // sub selects the lane group.  Loads G into LDS first (after a barrier, so a
@@ -62,7 +71,7 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
                                           uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
                                           uint8_t* __restrict__ status_out, int max_rounds, int warm_cap, int64_t b0,
                                           int64_t b1, int64_t g_first, int64_t g_step,
-                                          unsigned long long (&cacc)[NMF_BPP_COUNTERS]) {
+                                          unsigned long long (&cacc)[NMF_BPP_COUNTERS], BppExtras& ex) {
   constexpr int P = 64 / K;
   __shared__ double Gs[K * K];
   __shared__ double Gi[K * K];
@@ -508,8 +517,14 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
         }
       }
     }
-    if (valid) X[b * ldx + p] = (float)xfin;
+    if (valid) {
+      const float xs = (float)xfin;
+      X[b * ldx + p] = xs;
+      ex.dot += (double)xs * f;
+    }
     if (vprob && p == 0) {
+      ex.capped += (st & NMF_BPP_CAPPED) ? 1 : 0;
+      ex.fallback += (st & NMF_BPP_WARM_FALLBACK) ? 1 : 0;
       if (pinned) st |= NMF_BPP_PINNED;
       if (mask_out) mask_out[b] = F;
       if (rounds_out) rounds_out[b] = (uint8_t)(rounds < 255 ? rounds : 255);
@@ -545,18 +560,60 @@ __device__ __forceinline__ void flush_counters(const unsigned long long (&cacc)[
   }
 }
 
+// Block sums of the extras: the dot sum to dot_partial[blockIdx.x] (summed
+// in a fixed order, so the result does not depend on timing), the status
+// counts added to status_counts[0] (capped) and [1] (fell back).
+__device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __restrict__ dot_partial,
+                                             unsigned long long* __restrict__ status_counts) {
+  __shared__ double sd[kWaves];
+  __shared__ unsigned long long sc[kWaves][2];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double d = ex.dot;
+  unsigned long long c = ex.capped, f = ex.fallback;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    d += __shfl_xor(d, off, 64);
+    c += __shfl_xor(c, off, 64);
+    f += __shfl_xor(f, off, 64);
+  }
+  if (lane == 0) {
+    sd[wave] = d;
+    sc[wave][0] = c;
+    sc[wave][1] = f;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double bd = 0.0;
+    unsigned long long bc = 0, bf = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      bd += sd[w];
+      bc += sc[w][0];
+      bf += sc[w][1];
+    }
+    if (dot_partial) dot_partial[blockIdx.x] = bd;
+    if (status_counts) {
+      if (bc) atomicAdd(status_counts, bc);
+      if (bf) atomicAdd(status_counts + 1, bf);
+    }
+  }
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double* __restrict__ G,
                                              const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
                                              int64_t ldx, const uint64_t* mask_in,
                                              uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
                                              uint8_t* __restrict__ status_out, int max_rounds, int warm_cap,
-                                             unsigned long long* __restrict__ counters) {
+                                             unsigned long long* __restrict__ counters,
+                                             double* __restrict__ dot_partial,
+                                             unsigned long long* __restrict__ status_counts) {
   unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
+  BppExtras ex;
   const int wave = threadIdx.x >> 6;
   bpp_block<K>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0, batch,
-               (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves, cacc);
+               (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves, cacc, ex);
   if (counters) flush_counters(cacc, counters);
+  if (dot_partial || status_counts) flush_extras(ex, dot_partial, status_counts);
 }
 
 // Grouped form: a persistent walk over items, each a range of problems of
@@ -567,26 +624,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 56 ? 2
                                                      int max_rounds, int warm_cap,
                                                      unsigned long long* __restrict__ counters) {
   unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
+  BppExtras ex;  // not used here
   const int wave = threadIdx.x >> 6;
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     const nmf::BppItem it = items[i];
     bpp_block<K>(it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status, max_rounds, warm_cap,
-                 it.b0, it.b1, wave, kWaves, cacc);
+                 it.b0, it.b1, wave, kWaves, cacc, ex);
   }
   if (counters) flush_counters(cacc, counters);
+}
+
+constexpr int64_t kMaxBppBlocks = 1024;
+
+int64_t grid_blocks(int K, int64_t batch) {
+  const int64_t waves = nmf::cdiv(batch, 64 / K);
+  const int64_t blocks = nmf::cdiv(waves, kWaves);
+  return blocks < kMaxBppBlocks ? blocks : kMaxBppBlocks;
 }
 
 template <int K>
 int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X, int64_t ldx,
            const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds, uint8_t* status, int max_rounds,
-           int warm_cap, uint64_t* counters, hipStream_t s) {
-  constexpr int P = 64 / K;
-  const int64_t waves = nmf::cdiv(batch, P);
-  int64_t blocks = nmf::cdiv(waves, kWaves);
-  if (blocks > 1024) blocks = 1024;
+           int warm_cap, uint64_t* counters, double* dot_partial, uint64_t* status_counts, hipStream_t s) {
+  const int64_t blocks = grid_blocks(K, batch);
   hipLaunchKernelGGL(k_bpp<K>, dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
                      mask_out, rounds, status, max_rounds, warm_cap,
-                     reinterpret_cast<unsigned long long*>(counters));
+                     reinterpret_cast<unsigned long long*>(counters), dot_partial,
+                     reinterpret_cast<unsigned long long*>(status_counts));
   return nmf::launch_status("nnls_bpp_batched");
 }
 
@@ -594,15 +658,21 @@ int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, f
 
 namespace nmf {
 
+int64_t bpp_blocks(int k, int64_t batch) { return batch > 0 ? grid_blocks(bpp_class(k), batch) : 0; }
+
 int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X, int64_t ldx,
                const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds, uint8_t* status, int max_rounds,
-               int warm_cap, uint64_t* counters, hipStream_t s) {
+               int warm_cap, uint64_t* counters, hipStream_t s, double* dot_partial, uint64_t* status_counts) {
   if (batch == 0) return NMF_OK;
-  if (k <= 8) return launch<8>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
-  if (k <= 16) return launch<16>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
-  if (k <= 32) return launch<32>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
-  if (k <= 56) return launch<56>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
-  return launch<64>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, s);
+#define NMF_BPP_LAUNCH(KK)                                                                                   \
+  return launch<KK>(k, batch, G, R, ldr, X, ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, counters, \
+                    dot_partial, status_counts, s)
+  if (k <= 8) NMF_BPP_LAUNCH(8);
+  if (k <= 16) NMF_BPP_LAUNCH(16);
+  if (k <= 32) NMF_BPP_LAUNCH(32);
+  if (k <= 56) NMF_BPP_LAUNCH(56);
+  NMF_BPP_LAUNCH(64);
+#undef NMF_BPP_LAUNCH
 }
 
 int bpp_grouped_launch(int K, const BppItem* items, int64_t n, int grid, int max_rounds, int warm_cap,

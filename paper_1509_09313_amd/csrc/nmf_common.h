@@ -70,9 +70,15 @@ int rhs_csr_launch(int64_t rows, int64_t cols, int k, const int64_t* rowptr, con
 int local_update_launch(int solver, int k, int64_t rows, const double* G, const float* R, int64_t ldr, float* X,
                         int64_t ldx, hipStream_t s);
 
+// dot_partial (optional, bpp_blocks(k, batch) entries): per-block sums of
+// R[b][i] X[b][i] over the stored solutions; status_counts (optional, two
+// entries): the capped and fell-back problems are added to [0] and [1].
 int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X,
                int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds,
-               uint8_t* status, int max_rounds, int warm_cap, uint64_t* counters, hipStream_t s);
+               uint8_t* status, int max_rounds, int warm_cap, uint64_t* counters, hipStream_t s,
+               double* dot_partial = nullptr, uint64_t* status_counts = nullptr);
+// workgroups (and dot_partial entries) of a bpp_launch of this size
+int64_t bpp_blocks(int k, int64_t batch);
 
 // Zero-fills a rows x cols FP32 block with leading dimension ld (a kernel, so
 // it is safe inside captured graphs).

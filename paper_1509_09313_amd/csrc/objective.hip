@@ -327,6 +327,9 @@ int dot_f32_launch(int64_t len, const float* a, const float* b, double* out, dou
   return launch_status("dot reduce");
 }
 
+int trace_finish_launch(int nblocks, const double* partial, int k, const double* GW, const double* GH,
+                        const double* fro2, double* out, double* r_copy, hipStream_t s);
+
 // {r, res2, fro2} of the trace expansion, with cross = <a, b> over len FP32
 // elements (a = R, b = the factor just solved for) and the Gram inner product
 // <G_W, G_H>_F; used by the ANLS driver too.  Two launches.
@@ -335,6 +338,13 @@ int trace_objective_launch(int64_t len, const float* a, const float* b, int k, c
                            hipStream_t s) {
   hipLaunchKernelGGL(k_dot<float>, dim3(nblocks), dim3(kRedThreads), 0, s, len, a, b, partial);
   NMF_TRY(launch_status("objective cross term"));
+  return trace_finish_launch(nblocks, partial, k, GW, GH, fro2, out, r_copy, s);
+}
+
+// The same with the cross term already summed per block into partial[0 .. nblocks)
+// (the BPP kernel does so for the rows it solves).
+int trace_finish_launch(int nblocks, const double* partial, int k, const double* GW, const double* GH,
+                        const double* fro2, double* out, double* r_copy, hipStream_t s) {
   hipLaunchKernelGGL(k_trace_finish, dim3(1), dim3(kRedThreads), 0, s, (int64_t)nblocks, partial, (int64_t)k * k, GW,
                      GH, fro2, out, r_copy);
   return launch_status("objective finish");
