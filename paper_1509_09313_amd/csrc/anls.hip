@@ -143,7 +143,8 @@ int check_matrix(const nmf_matrix* A) {
   return NMF_OK;
 }
 
-int rhs(const nmf_matrix* A, int side, int k, int prec, const float* Y, float* R, void* scratch, hipStream_t s) {
+int rhs(const nmf_matrix* A, int side, int k, int prec, const float* Y, float* R, void* scratch, hipStream_t s,
+        bool y_ready = false) {
   if (A->kind == NMF_CSR) {
     float* ypad = static_cast<float*>(scratch);
     if (side == NMF_SIDE_W)
@@ -151,7 +152,7 @@ int rhs(const nmf_matrix* A, int side, int k, int prec, const float* Y, float* R
     return nmf::rhs_csr_launch(A->n, A->m, k, A->rowptr_t, A->colidx_t, A->vals_t, Y, k, R, k, ypad, s);
   }
   const void* bt = side == NMF_SIDE_W ? A->A_bf16 : A->At_bf16;
-  return nmf::rhs_dense_launch(side, A->m, A->n, k, A->A, A->lda, bt, Y, k, R, k, prec, scratch, s);
+  return nmf::rhs_dense_launch(side, A->m, A->n, k, A->A, A->lda, bt, Y, k, R, k, prec, scratch, s, y_ready);
 }
 
 int collect(int k, int64_t batch, int64_t stride, const double* G, const float* R, const uint64_t* masks,
@@ -260,8 +261,15 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     if (o->collect)
       NMF_TRY(collect(k, m, o->collect_stride_w, P.GH, P.RW, P.MW, o->coll_phi_w, o->coll_mask_w, o->coll_cap_w,
                       &hc[0], s));
+    // BF16x3: the Gram pass over W also writes W's transposed split, the Y
+    // planes of the W^T A product that follows
+    const bool split_in_gram = A->kind == NMF_DENSE && o->prec == NMF_BF16X3;
+    uint16_t *yth = nullptr, *ytl = nullptr;
+    int64_t ldt = 0;
+    int KP = 0;
+    if (split_in_gram) nmf::bf16x3_y_planes(NMF_SIDE_H, m, n, k, P.rhs_h, &yth, &ytl, &ldt, &KP);
     rec(ev(t, NMF_PH_GRAM_W, 0));
-    NMF_TRY(nmf::gram_launch(m, k, W, k, P.GW, P.gpart, P.gblocks, s));
+    NMF_TRY(nmf::gram_launch(m, k, W, k, P.GW, P.gpart, P.gblocks, s, yth, ytl, ldt, KP));
     rec(ev(t, NMF_PH_GRAM_W, 1));
     if (trace && bpp) {
       NMF_TRY(nmf::trace_finish_launch((int)nmf::bpp_blocks(k, m), P.bdot, k, P.GW, P.GH, A->fro2, P.obj,
@@ -273,7 +281,7 @@ extern "C" int nmf_anls_iter(const nmf_matrix* A, int k, float* W, float* Ht, in
     // ---- H update: H = argmin ||A - W H||, from W^T W and W^T A
     {
       MarkScope mark(ev(t, NMF_PH_RHS_H, 0), ev(t, NMF_PH_RHS_H, 1));
-      NMF_TRY(rhs(A, NMF_SIDE_H, k, o->prec, W, P.RH, P.rhs_h, s));
+      NMF_TRY(rhs(A, NMF_SIDE_H, k, o->prec, W, P.RH, P.rhs_h, s, split_in_gram));
     }
     rec(ev(t, NMF_PH_INFER_H, 0));
     if (o->warm == NMF_WARM_LEARNED)

@@ -27,7 +27,8 @@ constexpr int kMaxBlocks = 1024;
 template <int KW>
 __device__ __forceinline__ void gram_tiles(int64_t rows, int k, const float* __restrict__ X, int64_t ldx,
                                            int64_t t_begin, int64_t t_end, int64_t t_step, double* __restrict__ out,
-                                           int64_t out_stride) {
+                                           int64_t out_stride, uint16_t* __restrict__ yth = nullptr,
+                                           uint16_t* __restrict__ ytl = nullptr, int64_t ldt = 0, int KP = 0) {
   constexpr int kRowsPerPass = kThreads / KW;
   constexpr int kLoads = kTileRows / kRowsPerPass;
   __shared__ float tile[kTileRows][64 + 4];
@@ -67,6 +68,17 @@ __device__ __forceinline__ void gram_tiles(int64_t rows, int k, const float* __r
 #pragma unroll
     for (int u = 0; u < kLoads; ++u) tile[lr + u * kRowsPerPass][lc] = stage[u];
     __syncthreads();
+    if (yth) {
+      // the tile's transposed BF16 split: plane row i, columns r0 .. r0 + 63
+      // (columns past k and rows past the end are staged as zero)
+      for (int e = t; e < KP * kTileRows; e += kThreads) {
+        const int i = e / kTileRows, rr = e - i * kTileRows;
+        const float x = tile[rr][i];
+        const uint16_t h = bf16_rne(x);
+        yth[i * ldt + r0 + rr] = h;
+        ytl[i * ldt + r0 + rr] = bf16_rne(x - bf16_to_f32(h));
+      }
+    }
     const int64_t tn = tl + t_step;
     if (tn < t_end) {
       const int64_t rb = tn * kTileRows + lr;
@@ -122,9 +134,11 @@ __device__ __forceinline__ void gram_tiles(int64_t rows, int k, const float* __r
 // reduction reads each entry's partials contiguously.
 template <int KW>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(int64_t rows, int k, const float* __restrict__ X,
-                                                           int64_t ldx, double* __restrict__ partial) {
+                                                           int64_t ldx, double* __restrict__ partial,
+                                                           uint16_t* __restrict__ yth, uint16_t* __restrict__ ytl,
+                                                           int64_t ldt, int KP) {
   const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
-  gram_tiles<KW>(rows, k, X, ldx, blockIdx.x, ntiles, gridDim.x, partial + blockIdx.x, gridDim.x);
+  gram_tiles<KW>(rows, k, X, ldx, blockIdx.x, ntiles, gridDim.x, partial + blockIdx.x, gridDim.x, yth, ytl, ldt, KP);
 }
 
 // Grouped form: item i sums its own tile range into its own k x k partial.
@@ -180,11 +194,18 @@ int gram_plan(int64_t rows, int k, Carver& c, double** partial, int* nblocks) {
 }
 
 int gram_launch(int64_t rows, int k, const float* X, int64_t ldx, double* G, double* partial, int nblocks,
-                hipStream_t s) {
+                hipStream_t s, uint16_t* yth, uint16_t* ytl, int64_t ldt, int KP) {
+  // the split needs every 64-row tile of the planes (ldt of them) and
+  // KP <= the staged width (32 or 64)
+  if (yth && (!ytl || ldt < cdiv(rows, kTileRows) * kTileRows || ldt % kTileRows || KP < k ||
+              KP > (k <= 32 ? 32 : 64)))
+    return fail(NMF_EINVAL, "gram: bad split planes");
   if (k <= 32)
-    hipLaunchKernelGGL(k_gram_partial<32>, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial);
+    hipLaunchKernelGGL(k_gram_partial<32>, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial, yth, ytl,
+                       ldt, KP);
   else
-    hipLaunchKernelGGL(k_gram_partial<64>, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial);
+    hipLaunchKernelGGL(k_gram_partial<64>, dim3(nblocks), dim3(kThreads), 0, s, rows, k, X, ldx, partial, yth, ytl,
+                       ldt, KP);
   NMF_TRY(launch_status("gram partial"));
   hipLaunchKernelGGL(k_gram_reduce, dim3((k * k + 3) / 4), dim3(256), 0, s, k, nblocks, partial, G);
   return launch_status("gram reduce");

@@ -52,12 +52,22 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---- internal launchers shared between translation units -------------------
 int gram_plan(int64_t rows, int k, Carver& c, double** partial, int* nblocks);
+// With yth (optional) the kernel also writes the transposed BF16 split of X
+// (hi to yth, lo to ytl: KP x ldt, X row r at column r, zero for columns
+// k <= i < KP and rows rows <= r < ldt; ldt a multiple of 64): the Y planes
+// of a BF16x3 product whose contraction runs over the rows of X.
 int gram_launch(int64_t rows, int k, const float* X, int64_t ldx, double* G, double* partial,
-                int nblocks, hipStream_t s);
+                int nblocks, hipStream_t s, uint16_t* yth = nullptr, uint16_t* ytl = nullptr, int64_t ldt = 0,
+                int KP = 0);
 
 int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, void** scratch);
+// y_ready: (BF16x3) the transposed Y planes in scratch are already written
 int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* Bt,
-                     const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s);
+                     const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s,
+                     bool y_ready = false);
+// The transposed Y planes of a BF16x3 product inside its scratch block
+void bf16x3_y_planes(int side, int64_t m, int64_t n, int k, void* scratch, uint16_t** yth, uint16_t** ytl,
+                     int64_t* ldt, int* KP);
 
 // CSR products.  csr_pad_ld: a leading dimension for Y whose rows never
 // straddle a 128-byte line; with ypad (cols x csr_pad_ld(k) floats) Y is
@@ -115,6 +125,16 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// The BF16 split of the BF16x3 products: hi = bf16_rne(x), lo =
+// bf16_rne(x - hi) (round to nearest even; x - hi is exact in FP32).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const uint32_t bias = 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)((u + bias) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll

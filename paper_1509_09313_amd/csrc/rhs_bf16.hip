@@ -12,14 +12,6 @@
 
 namespace {
 
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  const uint32_t u = __float_as_uint(x);
-  const uint32_t bias = 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)((u + bias) >> 16);
-}
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
 // Padded BF16 operand: B (rows x cols) as two row-major planes of Rp x Cp
 // BF16 values, Rp = rows rounded up to kTR, Cp = cols rounded up to kTC, zero
 // in the padding: the hi plane, then the lo plane.  Row-major rows keep the 8
@@ -477,8 +469,17 @@ int64_t bf16x3_chain(int side, int64_t m, int64_t n, int k) {
   return 3 * p.kcps * kTC;
 }
 
+void bf16x3_y_planes(int side, int64_t m, int64_t n, int k, void* scratch, uint16_t** yth, uint16_t** ytl,
+                     int64_t* ldt, int* KP) {
+  const Bf16Plan p = bf16_plan(side, m, n, k, 0);
+  *yth = static_cast<uint16_t*>(scratch);
+  *ytl = *yth + (size_t)p.KP * p.ldt;
+  *ldt = p.ldt;
+  *KP = p.KP;
+}
+
 int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const float* Y, int64_t ldy, float* R,
-                  int64_t ldr, void* scratch, hipStream_t s) {
+                  int64_t ldr, void* scratch, hipStream_t s, bool y_ready) {
   const int KP = k <= 32 ? 32 : 64;
   const Bf16Plan p = bf16_plan(side, m, n, k, bf16_capacity(KP));
   if (p.rows == 0) return NMF_OK;
@@ -488,9 +489,11 @@ int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const f
   // the partials follow the planes at the next 256-byte boundary (as carved)
   const size_t plane_bytes = (size_t)2 * p.KP * p.ldt * sizeof(uint16_t);
   float* partial = reinterpret_cast<float*>(static_cast<char*>(scratch) + ((plane_bytes + 255) & ~size_t(255)));
-  hipLaunchKernelGGL(k_split_y, dim3((unsigned)cdiv(p.ldt, 64)), dim3(256), 0, s, p.K, k, p.KP, Y, ldy, yth, ytl,
-                     p.ldt);
-  NMF_TRY(launch_status("rhs bf16x3: split Y"));
+  if (!y_ready) {
+    hipLaunchKernelGGL(k_split_y, dim3((unsigned)cdiv(p.ldt, 64)), dim3(256), 0, s, p.K, k, p.KP, Y, ldy, yth, ytl,
+                       p.ldt);
+    NMF_TRY(launch_status("rhs bf16x3: split Y"));
+  }
   float* P = p.S > 1 ? partial : R;
   const int64_t ldp = p.S > 1 ? k : ldr;
   const int64_t stride = p.S > 1 ? p.rows * k : 0;

@@ -597,7 +597,7 @@ int launch_h_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const
 namespace nmf {
 int bf16x3_plan(int side, int64_t m, int64_t n, int k, Carver& c, void** scratch);
 int bf16x3_launch(int side, int64_t m, int64_t n, int k, const void* Bt, const float* Y, int64_t ldy, float* R,
-                  int64_t ldr, void* scratch, hipStream_t s);
+                  int64_t ldr, void* scratch, hipStream_t s, bool y_ready);
 int64_t bf16x3_chain(int side, int64_t m, int64_t n, int k);
 }
 
@@ -617,8 +617,9 @@ int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, v
 }
 
 int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int64_t lda, const void* Bt,
-                     const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s) {
-  if (prec == NMF_BF16X3) return bf16x3_launch(side, m, n, k, Bt, Y, ldy, R, ldr, scratch, s);
+                     const float* Y, int64_t ldy, float* R, int64_t ldr, int prec, void* scratch, hipStream_t s,
+                     bool y_ready) {
+  if (prec == NMF_BF16X3) return bf16x3_launch(side, m, n, k, Bt, Y, ldy, R, ldr, scratch, s, y_ready);
   if (side == NMF_SIDE_W) {
     if (m == 0) return NMF_OK;
     float* yt = static_cast<float*>(scratch);
