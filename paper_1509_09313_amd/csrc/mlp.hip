@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_features(int k, int64_t batch, int64_t 
 }
 
 // ------------------------------------------------------------- training --
-constexpr int kSB = 8;  // samples per block in the activation pass
+constexpr int kSB = 4;  // samples per block in the activation pass (8: 1.54 ms per 20 steps, 4: 1.17 ms; same parameters)
 
 __device__ __forceinline__ int64_t sample_index(int64_t step, int64_t pos, int64_t nsamp, int sequential,
                                                 const int64_t* __restrict__ order, int batch) {
