@@ -1003,12 +1003,9 @@ def ksweep_mode(a):
             W, Ht = torch.empty_like(W0), torch.empty_like(Ht0)
             t, ph, _ = _form_run(L, M, k, W, Ht, W0, Ht0, T, a.steps, a.warmup, **kw)
             r = float(L.nmf_objective(M, W, Ht)[0])
-            o = o_s = None
+            o = None
             if ref is not None and name.startswith("bpp"):
                 o = ref["k"][str(k)]["r_full"][-1]
-                # the FP64 oracle's own time for these iterations, recorded when the stored run was
-                # written (on the machine that wrote it)
-                o_s = ref["k"][str(k)]["oracle_seconds"] / ref["iterations"]
             ms = t / (a.steps * T) * 1e3
             split = {"MM": ph["rhs_w"] + ph["rhs_h"], "NLS": ph["bpp_w"] + ph["bpp_h"],
                      "Gram": ph["gram_w"] + ph["gram_h"]}
@@ -1018,7 +1015,7 @@ def ksweep_mode(a):
             mm_gbs = mm_bytes / (split["MM"] * 1e-3) / 1e9
             rows.append({"k": k, "iters_per_s": 1e3 / ms, "ms_per_iter": ms, "split_ms": split, "final_r": r,
                          "oracle_r": o, "abs_dr_vs_oracle": None if o is None else abs(r - o),
-                         "mm_GBps": mm_gbs, "mm_hbm_frac": mm_gbs / 8000.0, "oracle_s_per_iter_recorded": o_s})
+                         "mm_GBps": mm_gbs, "mm_hbm_frac": mm_gbs / 8000.0})
             print(f"# {name} k={k}: {ms:.2f} ms/iter (MM {split['MM']:.2f} at {mm_gbs:.0f} GB/s, "
                   f"NLS {split['NLS']:.2f}, Gram {split['Gram']:.2f}), r {r:.8f}", file=sys.stderr, flush=True)
             del W, Ht, W0, Ht0
