@@ -303,7 +303,13 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
               }
               vt[a] = false;
             }
-            const double ra = ok ? 1.0 / col[a] : 0.0;
+            // 1 / pivot: hardware estimate and two Newton steps, as in the
+            // elimination below (W side at 10^6 x 2400, k = 30: 0.919 -> 0.902 ms
+            // against the IEEE division)
+            double ra = __builtin_amdgcn_rcp(col[a]);
+            ra = fma(ra, fma(-col[a], ra, 1.0), ra);
+            ra = fma(ra, fma(-col[a], ra, 1.0), ra);
+            ra = ok ? ra : 0.0;
             rinv[a] = ra;
             dd[a] = ok ? col[a] : 0.0;
 #pragma unroll
