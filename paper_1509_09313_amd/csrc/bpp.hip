@@ -82,6 +82,7 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
   __shared__ double colv[kWaves][kSlots];
   __shared__ double rfv[kWaves][kSlots];
   __shared__ double dgv[kWaves][P == 1 ? 65 : 1];
+  __shared__ int pix[kWaves][P == 1 ? 65 : 1];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool lane_in = lane < P * K;
@@ -369,13 +370,15 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
         double* dgw = &dgv[wave][0];
         double r[K];
         {
-          uint64_t rem = Pv;
+          // each pivot lane enters its index at its packed slot, so the
+          // gather's addresses need no serial scan of the pivot set
+          int* pw = &pix[wave][0];
+          pw[slot] = p;
+          wave_lds_sync();
 #pragma unroll
           for (int c = 0; c < K; ++c) {
             // positions before the pivots are never read; they load row 0
-            const bool real = c >= off;
-            const int jc = real ? __ffsll((unsigned long long)rem) - 1 : 0;
-            rem = real ? (rem & (rem - 1ull)) : rem;
+            const int jc = c >= off ? pw[c] : 0;
             r[c] = Mrow[jc * K + p];
           }
         }
