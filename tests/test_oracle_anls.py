@@ -95,6 +95,32 @@ def test_fixed_point_planted_exact(oracle_lib):
     assert fr < 1e-18 * fa
 
 
+def test_rank1_closed_form(oracle_lib):
+    """k = 1 and A = u v^T with u, v > 0: every NNLS is a scalar with a
+    positive solution, so one iteration of Algorithm 1 from h > 0 gives
+    w = A h / (h.h) = u (v.h)/(h.h), then h' = A^T w / (w.w) = v (h.h)/(v.h),
+    and w h'^T = A exactly (closed form written out by hand)."""
+    rng = np.random.default_rng(33)
+    m, n = 40, 30
+    u = rng.integers(1, 5, m).astype(np.float64)
+    v = rng.integers(1, 5, n).astype(np.float64)
+    A = np.outer(u, v).astype(np.float32)          # small integers: exact in FP32
+    h = rng.uniform(0.5, 1.5, n)
+    res = oracle.anls(1, rng.uniform(size=(m, 1)), h[:, None], 1, dense=A)
+    w_ref = u * (v @ h) / (h @ h)
+    h_ref = v * (h @ h) / (v @ h)
+    np.testing.assert_allclose(res["W"][:, 0], w_ref, rtol=1e-13)
+    np.testing.assert_allclose(res["Ht"][:, 0], h_ref, rtol=1e-13)
+    fa, fr = oracle.objective_dense(A, res["W"], res["Ht"])
+    assert fr < 1e-24 * fa
+    # after the W half-step the residual is u (v - h (v.h)/(h.h))^T: relative
+    # size sqrt(1 - (v.h)^2 / ((v.v)(h.h))); after the H half-step zero (the
+    # trace form cancels to about sqrt(eps))
+    r_half = np.sqrt(1.0 - (v @ h) ** 2 / ((v @ v) * (h @ h)))
+    assert abs(res["r_half"][0] - r_half) < 1e-7
+    assert res["r_full"][0] < 1e-6
+
+
 def test_warm_equals_cold_trajectory(oracle_lib):
     w, A, W0, H0 = config1_inputs()
     cold = oracle.anls(w.k, W0, H0, w.iters, dense=A)
