@@ -5,7 +5,10 @@
 // multiply-adds per row: each block stages a tile of rows in LDS and every
 // thread accumulates a 4 x 4 block of the upper triangle of G for one slice of
 // the tile's rows; slices and then blocks are combined in a fixed order, so
-// the FP64 result does not depend on scheduling.
+// the FP64 result does not depend on scheduling.  Optionally the same pass
+// writes X's transposed BF16 split (the Y planes of a BF16x3 product that
+// contracts over the rows of X) from the staged tiles, sparing that product
+// its own pass over X.
 #include <mutex>
 
 #include "batched.h"
