@@ -74,6 +74,33 @@ def test_config1_warm_prev_matches_cold():
     assert sum(s["bpp_w"][0] for s in st[1:]) < ref["rounds_w"][1:].sum()
 
 
+def test_config1_status_counts():
+    """The capped and fell-back problem counts of the iteration records (summed
+    by the BPP kernel): with a round cap of 3 the oracle caps 136 problems in
+    the first iteration of config 1 and 222 over all 10, and the GPU the same
+    (within rounding of problems at the cap's edge); previous-iterate
+    starts held to one round fall back whenever the stored set is not already
+    optimal, and never with a generous hold."""
+    w = C.WORKLOADS["c1"]
+    A = C.config1_matrix(w.m, w.n, w.rank)
+    W0, H0 = C.init_w(w.seed, w.m, w.k), C.init_ht(w.seed, w.n, w.k)
+    M = L.Matrix(dense=cuda(A))
+    # one iteration solves the same problems on both sides (up to rounding);
+    # over ten the capped returns let the iterates drift apart a little
+    for iters, slack in ((1, 1), (w.iters, 2)):
+        ref = oracle.anls(w.k, W0, H0, iters, dense=A, max_rounds=3)
+        _, _, st = run_gpu(M, w.k, W0, H0, iters, max_rounds=3)
+        capped = sum(s["capped"] for s in st)
+        print(f"{iters} iterations, capped: gpu {capped}, oracle {ref['capped']}")
+        assert ref["capped"] > 0 and abs(capped - ref["capped"]) <= max(slack, ref["capped"] // 50)
+    _, _, st1 = run_gpu(M, w.k, W0, H0, w.iters, warm=L.NMF_WARM_PREV, warm_cap=1)
+    _, _, st50 = run_gpu(M, w.k, W0, H0, w.iters, warm=L.NMF_WARM_PREV, warm_cap=50)
+    fb1, fb50 = sum(s["fallback"] for s in st1), sum(s["fallback"] for s in st50)
+    print(f"fallbacks: hold 1 round {fb1}, hold 50 rounds {fb50}")
+    assert fb1 > 0 and fb50 == 0
+    assert all(s["capped"] == 0 for s in st1 + st50)
+
+
 def test_sparse_small_trajectory():
     w = C.WORKLOADS["c3s"]
     rp, ci, va = C.sparse_csr(w.seed, w.m, w.n, w.density, inst=w.inst)
