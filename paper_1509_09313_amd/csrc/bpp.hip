@@ -65,7 +65,12 @@ struct BppExtras {
 // sub selects the lane group.  Loads G into LDS first (after a barrier, so a
 // persistent loop may call it again with another G).  Round and solve
 // statistics are added to cacc (per lane; summed by the caller).
-template <int K, bool kRegGi = false>
+// Mark of a problem that the two-problem kernel left to the one-problem
+// kernel: a signalling NaN with a fixed payload in x_0 (arithmetic never
+// produces a signalling NaN, so no solution can carry it).
+constexpr uint32_t kDeferMark = 0xFFBADA55u;
+
+template <int K, bool kRegGi = false, bool kScan = false>
 __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, const float* __restrict__ R,
                                           int64_t ldr, float* __restrict__ X, int64_t ldx, const uint64_t* mask_in,
                                           uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
@@ -168,22 +173,55 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
   int64_t g = g_first;
   float f_next = 0.0f;
   uint64_t m_next = 0;
-  {
+  if constexpr (!kScan) {
     const int64_t b = b0 + g * P + sub;
     if (lane_in && b < b1 && p < k) f_next = R[b * ldr + p];
     if (lane_in && b < b1 && mask_in) m_next = mask_in[b];
   }
-  for (; b0 + g * P < b1; g += gstride) {
-    const int64_t b = b0 + g * P + sub;
-    const bool vprob = lane_in && b < b1;
-    const bool valid = vprob && p < k;
-    const double f = (double)f_next;
-    uint64_t F = vprob ? (m_next & all & ~pinned0) : 0ull;
-    {
+  // Scan form (one problem per wavefront): the problems are those of
+  // [b0, b1) whose x_0 holds kDeferMark, found 64 at a time (a chunk per
+  // wavefront, chunk g_first, g_first + g_step, ...) by a ballot.
+  static_assert(!kScan || P == 1, "the scan form needs one problem per wavefront");
+  int64_t sc0 = b0 + g_first * 64;
+  uint64_t sbits = 0;
+  auto marks = [&](int64_t c0) {
+    const int64_t bb = c0 + lane;
+    return __ballot(bb < b1 && __float_as_uint(X[bb * ldx]) == kDeferMark);
+  };
+  // the next marked problem: sbits holds the unvisited marks of chunk sc0
+  auto next_mark = [&]() {
+    while (sbits == 0ull) {
+      sc0 += g_step * 64;
+      if (sc0 >= b1) break;
+      sbits = marks(sc0);
+    }
+  };
+  if constexpr (kScan) {
+    sbits = sc0 < b1 ? marks(sc0) : 0ull;
+    next_mark();
+  }
+  for (; kScan ? sbits != 0ull : b0 + g * P < b1; g += gstride) {
+    int64_t b;
+    bool vprob;
+    double f;
+    uint64_t F;
+    if constexpr (kScan) {
+      b = sc0 + (__ffsll((unsigned long long)sbits) - 1);
+      sbits &= sbits - 1ull;
+      next_mark();
+      vprob = lane_in;
+      f = (vprob && p < k) ? (double)R[b * ldr + p] : 0.0;
+      F = (vprob && mask_in) ? (mask_in[b] & all & ~pinned0) : 0ull;
+    } else {
+      b = b0 + g * P + sub;
+      vprob = lane_in && b < b1;
+      f = (double)f_next;
+      F = vprob ? (m_next & all & ~pinned0) : 0ull;
       const int64_t bn = b0 + (g + gstride) * P + sub;
       f_next = (lane_in && bn < b1 && p < k) ? R[bn * ldr + p] : 0.0f;
       m_next = (lane_in && bn < b1 && mask_in) ? mask_in[bn] : 0ull;
     }
+    const bool valid = vprob && p < k;
     uint64_t pinned = pinned0;
     bool warm = F != 0;
     int alpha = 3, beta = k + 1, rounds = 0, since = 0;
@@ -566,10 +604,12 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
   cacc[5] += c_steps;
 }
 
-// Sums the per-lane statistics of the block and adds them to counters.
+// Sums the per-lane statistics of the block (NW wavefronts) and adds them to
+// counters.
+template <int NW = kWaves>
 __device__ __forceinline__ void flush_counters(const unsigned long long (&cacc)[NMF_BPP_COUNTERS],
                                                unsigned long long* __restrict__ counters) {
-  __shared__ unsigned long long cnt[kWaves][NMF_BPP_COUNTERS];
+  __shared__ unsigned long long cnt[NW][NMF_BPP_COUNTERS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int e = 0; e < NMF_BPP_COUNTERS; ++e) {
@@ -581,7 +621,7 @@ __device__ __forceinline__ void flush_counters(const unsigned long long (&cacc)[
   __syncthreads();
   if (t < NMF_BPP_COUNTERS) {
     unsigned long long s = 0;
-    for (int w = 0; w < kWaves; ++w) s += cnt[w][t];
+    for (int w = 0; w < NW; ++w) s += cnt[w][t];
     if (s) atomicAdd(counters + t, s);
   }
 }
@@ -589,10 +629,11 @@ __device__ __forceinline__ void flush_counters(const unsigned long long (&cacc)[
 // Block sums of the extras: the dot sum to dot_partial[blockIdx.x] (summed
 // in a fixed order, so the result does not depend on timing), the status
 // counts added to status_counts[0] (capped) and [1] (fell back).
+template <int NW = kWaves>
 __device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __restrict__ dot_partial,
                                              unsigned long long* __restrict__ status_counts) {
-  __shared__ double sd[kWaves];
-  __shared__ unsigned long long sc[kWaves][2];
+  __shared__ double sd[NW];
+  __shared__ unsigned long long sc[NW][2];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   double d = ex.dot;
   unsigned long long c = ex.capped, f = ex.fallback;
@@ -611,7 +652,7 @@ __device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __rest
   if (t == 0) {
     double bd = 0.0;
     unsigned long long bc = 0, bf = 0;
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < NW; ++w) {
       bd += sd[w];
       bc += sc[w][0];
       bf += sc[w][1];
@@ -622,6 +663,439 @@ __device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __rest
       if (bf) atomicAdd(status_counts + 1, bf);
     }
   }
+}
+
+// ---- Two problems per wavefront for 32 < k <= 64 ----------------------------
+// Whenever G_U^{-1} is available, a round eliminates over the smaller of F
+// and its complement in U, so it has at most floor(k / 2) pivots: at most
+// KK / 2 (28 or 32) for the class KK in {56, 64}.  The elimination needs only
+// the pivot rows, so a half-wavefront of 32 lanes holds them (pivot c of n_p,
+// in index order, at position KK / 2 - n_p + c) and one wavefront carries
+// two problems, lanes 0-31 and 32-63.  Lane h of a half owns indices h and
+// h + 32 (f, z, x, the dual y and the KKT test).  The non-pivot entries come
+// after the elimination from one product with the solved pivots:
+//     direct form  (pivots F):  y_i = sum_c G_{i,j_c} x_c - f_i
+//     inverse form (pivots A):  x_i = z_i - sum_c (G_U^{-1})_{i,j_c} v_c,
+// instead of riding along in the elimination as the one-problem kernel's
+// non-pivot rows do.  The pivot rows' arithmetic, and its order, is that of
+// the one-problem kernel; only the non-pivot entries round differently.
+// A round with more than KK / 2 pivots (G_U^{-1} unavailable, or a failed
+// pivot of the inverse form forcing the direct form with a large F) cannot
+// be held: the problem is left untouched except for kDeferMark in x_0, and
+// the one-problem kernel's scan form solves it from its start afterwards.
+// Blocks of 12 wavefronts (one block per CU, 3 wavefronts per SIMD, the most
+// that 168 VGPRs allow) share G and G_U^{-1} in LDS; G_U^{-1} comes from the
+// symmetric sweep run by the whole block.
+constexpr int kPairWaves = 12;
+constexpr int kPairL = 32;
+constexpr int kPairBlocks = 256;
+
+template <int KK>
+__global__ __launch_bounds__(kPairWaves * 64) void k_bpp_pair(int k, int64_t batch, const double* __restrict__ G,
+                                                   const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
+                                                   int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
+                                                   uint8_t* __restrict__ rounds_out, uint8_t* __restrict__ status_out,
+                                                   int max_rounds, int warm_cap,
+                                                   unsigned long long* __restrict__ counters,
+                                                   double* __restrict__ dot_partial,
+                                                   unsigned long long* __restrict__ status_counts) {
+  constexpr int L = kPairL;   // lanes per problem
+  constexpr int NP = KK / 2;  // pivot positions: k <= KK, so at most KK / 2 pivots
+  constexpr int NW = kPairWaves;
+  constexpr int NT = NW * 64;
+  constexpr int kPer = (KK * KK + NT - 1) / NT;  // sweep entries per thread
+  __shared__ double Gs[KK * KK];
+  __shared__ double Gi[KK * KK];
+  __shared__ double colv[NW][2][L];
+  __shared__ double rfv[NW][2][L + 1];
+  __shared__ double dgv[NW][2][L + 1];
+  __shared__ double vv[NW][2][2 * L];
+  __shared__ int pix[NW][2][L + 1];
+  // statistics in LDS (registers are the scarce resource here): per problem
+  // (solves, sum |F|, |F|^2, |F|^3, pivot steps) and per half-wavefront
+  // totals (the NMF_BPP_COUNTERS in order, then capped and fell-back counts)
+  __shared__ uint32_t pcnt[NW][2][5];
+  __shared__ unsigned long long tot[NW][2][NMF_BPP_COUNTERS + 2];
+  __shared__ double dsum[NW];
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int grp = lane >> 5, h = lane & 31;
+  if (h == 0)
+    for (int e = 0; e < NMF_BPP_COUNTERS + 2; ++e) tot[wave][grp][e] = 0;
+  const int i0 = h, i1 = h + L;
+  // LDS column of an owned index (indices >= KK exist only as padding lanes)
+  const int c1 = i1 < KK ? i1 : KK - 1;
+
+  for (int idx = t; idx < KK * KK; idx += NT) {
+    const int q = idx / KK, pp = idx - q * KK;
+    const double v = (q < k && pp < k) ? G[q * k + pp] : (q == pp ? 1.0 : 0.0);
+    Gs[idx] = v;
+    Gi[idx] = v;
+  }
+  __syncthreads();
+  const uint64_t all = (k == 64) ? ~0ull : (bit64(k) - 1ull);
+  double dmax = 0.0;
+  for (int q = 0; q < k; ++q) dmax = fmax(dmax, Gs[q * KK + q]);
+  uint64_t pinned0 = 0;
+  for (int q = 0; q < k; ++q)
+    if (Gs[q * KK + q] <= 1e-14 * dmax) pinned0 |= bit64(q);
+
+  // G_U^{-1} by the symmetric sweep over the unpinned indices in index order,
+  // on a row-major working copy W (row i in W[i][.]): sweeping j maps
+  // W_jj -> -1/d, W_jl -> W_jl / d, W_ij -> W_ij / d and
+  // W_il -> W_il - (W_ij / d) W_lj (d = W_jj), as the one-problem kernel does
+  // with one row per lane; then (G_U^{-1})_{q,p} = -W[p][q] on U x U.
+  bool inv_ok = true;
+  for (int j = 0; j < k; ++j) {
+    if ((pinned0 >> j) & 1ull) continue;
+    const double d = Gi[j * KK + j];
+    if (!(d > 1e-6 * Gs[j * KK + j])) inv_ok = false;
+    const double inv = 1.0 / d;
+    double nv[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = t + e * NT;
+      nv[e] = 0.0;
+      if (idx < KK * KK) {
+        const int i = idx / KK, l = idx - i * KK;
+        const double wil = Gi[idx], wij = Gi[i * KK + j], wlj = Gi[l * KK + j];
+        if (i == j) {
+          nv[e] = l == j ? -inv : wil * inv;
+        } else {
+          const double m = wij * inv;
+          nv[e] = l == j ? m : wil - m * wlj;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = t + e * NT;
+      if (idx < KK * KK) Gi[idx] = nv[e];
+    }
+    __syncthreads();
+  }
+  {
+    double nv[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = t + e * NT;
+      nv[e] = 0.0;
+      if (idx < KK * KK) {
+        const int q = idx / KK, pl = idx - q * KK;
+        const bool inU = q < k && pl < k && !((pinned0 >> q) & 1ull) && !((pinned0 >> pl) & 1ull);
+        nv[e] = inU ? -Gi[pl * KK + q] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = t + e * NT;
+      if (idx < KK * KK) Gi[idx] = nv[e];
+    }
+    __syncthreads();
+  }
+
+  double dot = 0.0;
+  uint32_t* pc = &pcnt[wave][grp][0];
+  unsigned long long* tg = &tot[wave][grp][0];
+  int* pw = &pix[wave][grp][0];
+  double* colw = &colv[wave][grp][0];
+  double* rfw = &rfv[wave][grp][0];
+  double* dgw = &dgv[wave][grp][0];
+  double* vw = &vv[wave][grp][0];
+
+  const int64_t npair = (batch + 1) / 2;
+  const int64_t gstride = (int64_t)gridDim.x * NW;
+  int64_t g = (int64_t)blockIdx.x * NW + wave;
+  float fn0 = 0.0f, fn1 = 0.0f;
+  uint64_t mn = 0;
+  {
+    const int64_t b = 2 * g + grp;
+    if (g < npair && b < batch) {
+      if (i0 < k) fn0 = R[b * ldr + i0];
+      if (i1 < k) fn1 = R[b * ldr + i1];
+      if (mask_in) mn = mask_in[b];
+    }
+  }
+  for (; g < npair; g += gstride) {
+    const int64_t b = 2 * g + grp;
+    const bool vprob = b < batch;
+    const bool val0 = vprob && i0 < k, val1 = vprob && i1 < k;
+    const double f0 = (double)fn0, f1 = (double)fn1;
+    uint64_t F = vprob ? (mn & all & ~pinned0) : 0ull;
+    {
+      const int64_t bn = 2 * (g + gstride) + grp;
+      const bool vn = g + gstride < npair && bn < batch;
+      fn0 = (vn && i0 < k) ? R[bn * ldr + i0] : 0.0f;
+      fn1 = (vn && i1 < k) ? R[bn * ldr + i1] : 0.0f;
+      mn = (vn && mask_in) ? mask_in[bn] : 0ull;
+    }
+    uint64_t pinned = pinned0;
+    bool warm = F != 0;
+    int alpha = 3, beta = k + 1, rounds = 0, since = 0;
+    int st = 0;
+    bool done = !vprob, defer = false;
+    bool forceG = false;
+    if (h == 0)
+      for (int e = 0; e < 5; ++e) pc[e] = 0;
+    // stores a finished problem's x (as FP32) and its share of the dot sum
+    auto finish = [&](double x0, double x1) {
+      if (val0) {
+        const float xs = (float)x0;
+        X[b * ldx + i0] = xs;
+        dot += (double)xs * f0;
+      }
+      if (val1) {
+        const float xs = (float)x1;
+        X[b * ldx + i1] = xs;
+        dot += (double)xs * f1;
+      }
+    };
+    // unconstrained solution z = G_U^{-1} f at the owned indices
+    double z0 = 0.0, z1 = 0.0;
+    if (inv_ok) {
+      vw[i0] = f0;
+      vw[i1] = f1;
+      wave_lds_sync();
+      for (int q = 0; q < k; ++q) {
+        const double fq = vw[q];
+        z0 += Gi[q * KK + i0] * fq;
+        z1 += Gi[q * KK + c1] * fq;
+      }
+      wave_lds_sync();
+    }
+
+    while (__ballot(!done) != 0) {
+      uint64_t Fe = done ? 0ull : F;
+      const uint64_t Ae = done ? 0ull : (all & ~pinned & ~F);
+      const bool useInv = inv_ok && !forceG && __popcll(Ae) < __popcll(Fe);
+      uint64_t Pv = useInv ? Ae : Fe;
+      if (__popcll(Pv) > NP) {
+        // more pivots than lanes: left to the one-problem kernel
+        defer = true;
+        done = true;
+        Fe = 0;
+        Pv = 0;
+      }
+      const double* Mrow = useInv ? Gi : Gs;
+      const int np = __popcll(Pv);
+      const int off = NP - np;
+      bool retry = false;
+      // each owned pivot enters its index, right-hand side and diagonal at
+      // its packed position
+      const bool pv0 = (Pv >> i0) & 1ull, pv1 = (Pv >> i1) & 1ull;
+      const int s0 = pv0 ? off + __popcll(Pv & (bit64(i0) - 1ull)) : L;
+      const int s1 = pv1 ? off + __popcll(Pv & (bit64(i1) - 1ull)) : L;
+      pw[s0] = i0;
+      rfw[s0] = useInv ? z0 : f0;
+      dgw[s0] = Mrow[i0 * KK + i0];
+      pw[s1] = i1;
+      rfw[s1] = useInv ? z1 : f1;
+      dgw[s1] = Mrow[c1 * KK + c1];
+      wave_lds_sync();
+      const bool mine = h >= off && h < NP;
+      const int jh = mine ? pw[h] : 0;
+      double r[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+        // positions before the pivots are never read; they load row 0
+        const int jc = c >= off ? pw[c] : 0;
+        r[c] = Mrow[jc * KK + jh];
+      }
+      double rf = mine ? rfw[h] : 0.0, mypiv = 1.0;
+      bool myok = mine;
+      wave_lds_sync();
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        if (__ballot(c >= off) == 0ull) continue;
+        const bool act = c >= off;
+        // this step's pivot lane, tested here (an opaque copy of c keeps the
+        // compiler from holding 32 precomputed lane masks through the loop)
+        int cs = c;
+        asm volatile("" : "+s"(cs));
+        const bool pl = h == cs;
+        colw[h] = r[c];
+        rfw[h] = rf;
+        wave_lds_sync();
+        const double piv = colw[c];
+        const double zj = rfw[c];
+        bool use = act;
+        if (act && !(piv > 1e-12 * dgw[c])) {
+          use = false;
+          if (pl) myok = false;
+          const int j = pw[c];
+          if (useInv) {
+            retry = true;
+          } else {
+            F &= ~bit64(j);
+            Fe &= ~bit64(j);
+            pinned |= bit64(j);
+            st |= NMF_BPP_SINGULAR;
+          }
+        }
+        double inv = __builtin_amdgcn_rcp(piv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        inv = use ? inv : 0.0;
+        const double mlt = (use && !pl) ? r[c] * inv : 0.0;
+        if (use && pl) mypiv = piv;
+        // (the pivot row is read eight entries at a time, so that its loads
+        // do not all stay in flight beside the row)
+#pragma unroll
+        for (int q = c + 1; q < NP; ++q) {
+          if ((q - c) % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+          r[q] -= mlt * colw[q];
+        }
+        rf -= mlt * zj;
+        wave_lds_sync();
+      }
+      // the solved pivots by position (zero before the pivots and for a
+      // failed pivot), then the owned entries
+      vw[h] = myok ? rf / mypiv : 0.0;
+      wave_lds_sync();
+      double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        if (__ballot(c >= off) == 0ull) continue;
+        if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+        const int jc = c >= off ? pw[c] : 0;
+        const double vc = vw[c];
+        acc0 += Mrow[jc * KK + i0] * vc;
+        acc1 += Mrow[jc * KK + c1] * vc;
+      }
+      const double own0 = vw[s0 < L ? s0 : 0], own1 = vw[s1 < L ? s1 : 0];
+      wave_lds_sync();
+      const bool inF0 = (Fe >> i0) & 1ull, inF1 = (Fe >> i1) & 1ull;
+      const bool pin0 = (pinned >> i0) & 1ull, pin1 = (pinned >> i1) & 1ull;
+      double x0, y0, x1, y1;
+      if (useInv) {
+        x0 = inF0 ? z0 - acc0 : 0.0;
+        y0 = (inF0 || pin0) ? 0.0 : -own0;
+        x1 = inF1 ? z1 - acc1 : 0.0;
+        y1 = (inF1 || pin1) ? 0.0 : -own1;
+      } else {
+        x0 = inF0 ? own0 : 0.0;
+        y0 = inF0 ? 0.0 : acc0 - f0;
+        x1 = inF1 ? own1 : 0.0;
+        y1 = inF1 ? 0.0 : acc1 - f1;
+      }
+      const bool live = !done && !retry;
+      const bool viol0 = val0 && live && !pin0 && (inF0 ? (x0 < 0.0) : (y0 < 0.0));
+      const bool viol1 = val1 && live && !pin1 && (inF1 ? (x1 < 0.0) : (y1 < 0.0));
+      const uint64_t bal0 = __ballot(viol0), bal1 = __ballot(viol1);
+      const int sh = grp * 32;
+      const uint64_t V = ((bal0 >> sh) & 0xffffffffull) | (((bal1 >> sh) & 0xffffffffull) << 32);
+      if (retry) forceG = true;
+      if (live) {
+        if (h == 0) {
+          const uint32_t nf = (uint32_t)__popcll(Fe);
+          pc[4] += (uint32_t)np;
+          if (nf) {
+            pc[0] += 1;
+            pc[1] += nf;
+            pc[2] += nf * nf;
+            pc[3] += nf * nf * nf;
+          }
+        }
+        ++rounds;
+        ++since;
+        if (V == 0) {
+          done = true;
+          finish(x0, x1);
+        } else if (warm && since >= warm_cap) {
+          st |= NMF_BPP_WARM_FALLBACK;
+          warm = false;
+          F = 0;
+          alpha = 3;
+          beta = k + 1;
+          since = 0;
+        } else if (rounds >= max_rounds) {
+          st |= NMF_BPP_CAPPED;
+          done = true;
+          finish(x0 > 0.0 ? x0 : 0.0, x1 > 0.0 ? x1 : 0.0);
+        } else {
+          const int nv = __popcll(V);
+          uint64_t S;
+          if (nv < beta) {
+            beta = nv;
+            alpha = 3;
+            S = V;
+          } else if (alpha >= 1) {
+            alpha -= 1;
+            S = V;
+          } else {
+            S = bit64(63 - __clzll((long long)V));
+          }
+          F ^= S;
+        }
+      }
+    }
+    if (vprob && defer) {
+      if (h == 0) X[b * ldx] = __uint_as_float(kDeferMark);
+    } else if (vprob) {
+      if (h == 0) {
+        tg[0] += (unsigned long long)rounds;
+        for (int e = 0; e < 5; ++e) tg[1 + e] += pc[e];
+        tg[6] += (st & NMF_BPP_CAPPED) ? 1 : 0;
+        tg[7] += (st & NMF_BPP_WARM_FALLBACK) ? 1 : 0;
+        if (pinned) st |= NMF_BPP_PINNED;
+        if (mask_out) mask_out[b] = F;
+        if (rounds_out) rounds_out[b] = (uint8_t)(rounds < 255 ? rounds : 255);
+        if (status_out) status_out[b] = (uint8_t)st;
+      }
+    }
+  }
+  // block sums: the dot partial in a fixed order, the counts by atomics
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o, 64);
+  if (lane == 0) dsum[wave] = dot;
+  __syncthreads();
+  if (t == 0) {
+    double bd = 0.0;
+    for (int w = 0; w < NW; ++w) bd += dsum[w];
+    if (dot_partial) dot_partial[blockIdx.x] = bd;
+  }
+  if (t < NMF_BPP_COUNTERS + 2) {
+    unsigned long long v = 0;
+    for (int w = 0; w < NW; ++w) v += tot[w][0][t] + tot[w][1][t];
+    if (t < NMF_BPP_COUNTERS) {
+      if (counters && v) atomicAdd(counters + t, v);
+    } else if (status_counts && v) {
+      atomicAdd(status_counts + (t - NMF_BPP_COUNTERS), v);
+    }
+  }
+}
+
+// The one-problem kernel's scan form: solves the problems that k_bpp_pair
+// marked, from their start sets; dot_partial has one entry per block.
+template <int K>
+__global__ __launch_bounds__(256) void k_bpp_deferred(int k, int64_t batch, const double* __restrict__ G,
+                                                      const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
+                                                      int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
+                                                      uint8_t* __restrict__ rounds_out,
+                                                      uint8_t* __restrict__ status_out, int max_rounds, int warm_cap,
+                                                      unsigned long long* __restrict__ counters,
+                                                      double* __restrict__ dot_partial,
+                                                      unsigned long long* __restrict__ status_counts) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t w0 = (int64_t)blockIdx.x * kWaves + wave, ws = (int64_t)gridDim.x * kWaves;
+  bool any = false;
+  for (int64_t c0 = w0 * 64; c0 < batch; c0 += ws * 64) {
+    const int64_t bb = c0 + lane;
+    any |= bb < batch && __float_as_uint(X[bb * ldx]) == kDeferMark;
+  }
+  if (!__syncthreads_or(any)) {
+    if (threadIdx.x == 0 && dot_partial) dot_partial[blockIdx.x] = 0.0;
+    return;
+  }
+  unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
+  BppExtras ex;
+  bpp_block<K, false, true>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0,
+                            batch, w0, ws, cacc, ex);
+  if (counters) flush_counters(cacc, counters);
+  if (dot_partial || status_counts) flush_extras(ex, dot_partial, status_counts);
 }
 
 template <int K>
@@ -668,23 +1142,48 @@ int64_t grid_blocks(int K, int64_t batch) {
   return blocks < kMaxBppBlocks ? blocks : kMaxBppBlocks;
 }
 
+// K in {56, 64}: the two-problem kernel's blocks, then the scan's (a chunk of
+// 64 problems per wavefront)
+int64_t pair_blocks(int64_t batch) {
+  const int64_t b = nmf::cdiv(nmf::cdiv(batch, 2), kPairWaves);
+  return b < kPairBlocks ? b : kPairBlocks;
+}
+int64_t scan_blocks(int64_t batch) {
+  const int64_t b = nmf::cdiv(nmf::cdiv(batch, 64), kWaves);
+  return b < kMaxBppBlocks ? b : kMaxBppBlocks;
+}
+int64_t launch_blocks(int K, int64_t batch) {
+  return K >= 56 ? pair_blocks(batch) + scan_blocks(batch) : grid_blocks(K, batch);
+}
+
 template <int K>
 int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X, int64_t ldx,
            const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds, uint8_t* status, int max_rounds,
            int warm_cap, uint64_t* counters, double* dot_partial, uint64_t* status_counts, hipStream_t s) {
-  const int64_t blocks = grid_blocks(K, batch);
-  hipLaunchKernelGGL(k_bpp<K>, dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
-                     mask_out, rounds, status, max_rounds, warm_cap,
-                     reinterpret_cast<unsigned long long*>(counters), dot_partial,
-                     reinterpret_cast<unsigned long long*>(status_counts));
-  return nmf::launch_status("nnls_bpp_batched");
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
+  unsigned long long* sc = reinterpret_cast<unsigned long long*>(status_counts);
+  if constexpr (K >= 56) {
+    const int64_t pb = pair_blocks(batch), db = scan_blocks(batch);
+    hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(kPairWaves * 64), 0, s, k, batch, G, R, ldr, X, ldx,
+                       mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
+    NMF_TRY(nmf::launch_status("nnls_bpp_batched (two problems per wavefront)"));
+    hipLaunchKernelGGL(k_bpp_deferred<K>, dim3((unsigned)db), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
+                       mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial ? dot_partial + pb : nullptr,
+                       sc);
+    return nmf::launch_status("nnls_bpp_batched (deferred problems)");
+  } else {
+    const int64_t blocks = grid_blocks(K, batch);
+    hipLaunchKernelGGL(k_bpp<K>, dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
+                       mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
+    return nmf::launch_status("nnls_bpp_batched");
+  }
 }
 
 }  // namespace
 
 namespace nmf {
 
-int64_t bpp_blocks(int k, int64_t batch) { return batch > 0 ? grid_blocks(bpp_class(k), batch) : 0; }
+int64_t bpp_blocks(int k, int64_t batch) { return batch > 0 ? launch_blocks(bpp_class(k), batch) : 0; }
 
 int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, float* X, int64_t ldx,
                const uint64_t* mask_in, uint64_t* mask_out, uint8_t* rounds, uint8_t* status, int max_rounds,

@@ -187,6 +187,60 @@ def test_bpp_pinned_and_singular():
     assert np.max(np.abs(res_gpu - res_orc)) <= 1e-5 * np.abs(res_orc).max()
 
 
+def test_bpp_deferred_problems():
+    """k > 32 with a singular G: G_U^{-1} is unavailable (the duplicate column
+    fails its sweep pivot), so every round eliminates over F, and problems
+    whose F outgrows the two-problem kernel's 28 pivot positions are finished
+    by the one-problem kernel from their start.  The oracle's final sets show
+    that such problems exist; statuses, fits and counters must not show where
+    a problem was solved."""
+    rng = np.random.default_rng(11)
+    k, batch = 48, 700
+    Cm = rng.uniform(0.0, 1.0, (150, k))
+    Cm[:, 5] = 0.0             # pinned from the start
+    Cm[:, 40] = Cm[:, 9]       # singular passive subsets
+    G = Cm.T @ Cm
+    xs = rng.uniform(0.2, 1.0, (batch, k)) * (rng.uniform(size=(batch, k)) < 0.5)
+    R = ((xs @ Cm.T + 0.05 * rng.standard_normal((batch, 150))) @ Cm).astype(np.float32)
+    ref = oracle.bpp_batched(G, R.astype(np.float64))
+    sizes = np.array([bin(int(m)).count("1") for m in ref[1]])
+    assert np.sum(sizes > 28) >= 50 and np.sum(sizes <= 28) >= 50, np.bincount(sizes)
+    cnt = torch.zeros(L.NMF_BPP_COUNTERS, dtype=torch.int64, device="cuda")
+    X, masks, rounds, st = (t.cpu().numpy() for t in L.nnls_bpp_batched(cuda(G), cuda(R), counters=cnt))
+    assert np.all(np.isfinite(X)) and np.all(X >= 0.0)
+    assert np.all(X[:, 5] == 0.0)
+    assert np.array_equal(st.astype(np.int32), ref[3])
+    res_gpu = Cm @ X.T.astype(np.float64)
+    res_orc = Cm @ ref[0].T
+    assert np.max(np.abs(res_gpu - res_orc)) <= 1e-5 * np.abs(res_orc).max()
+    assert cnt.cpu().numpy()[0] == rounds.astype(np.int64).sum()
+    assert np.mean(rounds.astype(np.int32) == ref[2]) >= 0.99
+
+
+@pytest.mark.parametrize("k", [40, 50, 64])
+def test_bpp_counters_two_problem_kernel(k):
+    """Round and pivot-step counters of the k > 32 kernels equal the sums of
+    the per-problem records; the stored sets reproduce the solutions."""
+    rng = np.random.default_rng(12 + k)
+    batch = 3001
+    G, R = nmf_like_problems(rng, k, batch)
+    cnt = torch.zeros(L.NMF_BPP_COUNTERS, dtype=torch.int64, device="cuda")
+    out = L.nnls_bpp_batched(cuda(G), cuda(R), counters=cnt)
+    ref = oracle.bpp_batched(G, R.astype(np.float64))
+    compare_bpp(G, R, out, ref)
+    c = cnt.cpu().numpy()
+    rounds = out[2].cpu().numpy().astype(np.int64)
+    assert c[0] == rounds.sum()
+    # warm start from the stored sets: one round each, same solutions
+    cnt.zero_()
+    out2 = L.nnls_bpp_batched(cuda(G), cuda(R), mask_in=out[1], counters=cnt)
+    r2 = out2[2].cpu().numpy()
+    m = out[1].cpu().numpy()
+    assert np.all(r2[m != 0] == 1)
+    assert cnt.cpu().numpy()[0] == r2.astype(np.int64).sum()
+    np.testing.assert_allclose(out2[0].cpu().numpy(), out[0].cpu().numpy(), rtol=1e-6, atol=1e-9)
+
+
 def test_bpp_cap_and_warm():
     rng = np.random.default_rng(6)
     k, batch = 30, 3000
