@@ -686,12 +686,15 @@ __device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __rest
 // Blocks of 12 wavefronts (one block per CU, 3 wavefronts per SIMD, the most
 // that 168 VGPRs allow) share G and G_U^{-1} in LDS; G_U^{-1} comes from the
 // symmetric sweep run by the whole block.
-constexpr int kPairWaves = 12;
-constexpr int kPairL = 32;
 constexpr int kPairBlocks = 256;
+// wavefronts per block of the class KK (one block per CU for KK >= 56; two
+// for KK = 32, whose blocks are smaller in LDS)
+constexpr int pair_waves(int KK) { return 12; }
+// lanes per problem: indices h and h + L belong to lane h of a group
+constexpr int pair_lanes(int KK) { return KK >= 56 ? 32 : KK / 2; }
 
 template <int KK>
-__global__ __launch_bounds__(kPairWaves * 64) void k_bpp_pair(int k, int64_t batch, const double* __restrict__ G,
+__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(3))) void k_bpp_pair(int k, int64_t batch, const double* __restrict__ G,
                                                    const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
                                                    int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
                                                    uint8_t* __restrict__ rounds_out, uint8_t* __restrict__ status_out,
@@ -699,27 +702,28 @@ __global__ __launch_bounds__(kPairWaves * 64) void k_bpp_pair(int k, int64_t bat
                                                    unsigned long long* __restrict__ counters,
                                                    double* __restrict__ dot_partial,
                                                    unsigned long long* __restrict__ status_counts) {
-  constexpr int L = kPairL;   // lanes per problem
-  constexpr int NP = KK / 2;  // pivot positions: k <= KK, so at most KK / 2 pivots
-  constexpr int NW = kPairWaves;
+  constexpr int L = pair_lanes(KK);  // lanes per problem
+  constexpr int P = 64 / L;          // problems per wavefront
+  constexpr int NP = KK / 2;         // pivot positions: k <= KK, so at most KK / 2 pivots
+  constexpr int NW = pair_waves(KK);
   constexpr int NT = NW * 64;
   constexpr int kPer = (KK * KK + NT - 1) / NT;  // sweep entries per thread
   __shared__ double Gs[KK * KK];
   __shared__ double Gi[KK * KK];
-  __shared__ double colv[NW][2][L];
-  __shared__ double rfv[NW][2][L + 1];
-  __shared__ double dgv[NW][2][L + 1];
-  __shared__ double vv[NW][2][2 * L];
-  __shared__ int pix[NW][2][L + 1];
+  __shared__ double colv[NW][P][L];
+  __shared__ double rfv[NW][P][L + 1];
+  __shared__ double dgv[NW][P][L + 1];
+  __shared__ double vv[NW][P][2 * L];
+  __shared__ int pix[NW][P][L + 1];
   // statistics in LDS (registers are the scarce resource here): per problem
   // (solves, sum |F|, |F|^2, |F|^3, pivot steps) and per half-wavefront
   // totals (the NMF_BPP_COUNTERS in order, then capped and fell-back counts)
-  __shared__ uint32_t pcnt[NW][2][5];
-  __shared__ unsigned long long tot[NW][2][NMF_BPP_COUNTERS + 2];
+  __shared__ uint32_t pcnt[NW][P][5];
+  __shared__ unsigned long long tot[NW][P][NMF_BPP_COUNTERS + 2];
   __shared__ double dsum[NW];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int grp = lane >> 5, h = lane & 31;
+  const int grp = lane / L, h = lane % L;
   if (h == 0)
     for (int e = 0; e < NMF_BPP_COUNTERS + 2; ++e) tot[wave][grp][e] = 0;
   const int i0 = h, i1 = h + L;
@@ -805,13 +809,13 @@ __global__ __launch_bounds__(kPairWaves * 64) void k_bpp_pair(int k, int64_t bat
   double* dgw = &dgv[wave][grp][0];
   double* vw = &vv[wave][grp][0];
 
-  const int64_t npair = (batch + 1) / 2;
+  const int64_t npair = (batch + P - 1) / P;  // problem groups, one per wavefront
   const int64_t gstride = (int64_t)gridDim.x * NW;
   int64_t g = (int64_t)blockIdx.x * NW + wave;
   float fn0 = 0.0f, fn1 = 0.0f;
   uint64_t mn = 0;
   {
-    const int64_t b = 2 * g + grp;
+    const int64_t b = P * g + grp;
     if (g < npair && b < batch) {
       if (i0 < k) fn0 = R[b * ldr + i0];
       if (i1 < k) fn1 = R[b * ldr + i1];
@@ -819,13 +823,13 @@ __global__ __launch_bounds__(kPairWaves * 64) void k_bpp_pair(int k, int64_t bat
     }
   }
   for (; g < npair; g += gstride) {
-    const int64_t b = 2 * g + grp;
+    const int64_t b = P * g + grp;
     const bool vprob = b < batch;
     const bool val0 = vprob && i0 < k, val1 = vprob && i1 < k;
     const double f0 = (double)fn0, f1 = (double)fn1;
     uint64_t F = vprob ? (mn & all & ~pinned0) : 0ull;
     {
-      const int64_t bn = 2 * (g + gstride) + grp;
+      const int64_t bn = P * (g + gstride) + grp;
       const bool vn = g + gstride < npair && bn < batch;
       fn0 = (vn && i0 < k) ? R[bn * ldr + i0] : 0.0f;
       fn1 = (vn && i1 < k) ? R[bn * ldr + i1] : 0.0f;
@@ -985,8 +989,9 @@ __global__ __launch_bounds__(kPairWaves * 64) void k_bpp_pair(int k, int64_t bat
       const bool viol0 = val0 && live && !pin0 && (inF0 ? (x0 < 0.0) : (y0 < 0.0));
       const bool viol1 = val1 && live && !pin1 && (inF1 ? (x1 < 0.0) : (y1 < 0.0));
       const uint64_t bal0 = __ballot(viol0), bal1 = __ballot(viol1);
-      const int sh = grp * 32;
-      const uint64_t V = ((bal0 >> sh) & 0xffffffffull) | (((bal1 >> sh) & 0xffffffffull) << 32);
+      const int sh = grp * L;
+      constexpr uint64_t mL = (1ull << L) - 1ull;
+      const uint64_t V = ((bal0 >> sh) & mL) | (((bal1 >> sh) & mL) << L);
       if (retry) forceG = true;
       if (live) {
         if (h == 0) {
@@ -1059,7 +1064,8 @@ __global__ __launch_bounds__(kPairWaves * 64) void k_bpp_pair(int k, int64_t bat
   }
   if (t < NMF_BPP_COUNTERS + 2) {
     unsigned long long v = 0;
-    for (int w = 0; w < NW; ++w) v += tot[w][0][t] + tot[w][1][t];
+    for (int w = 0; w < NW; ++w)
+      for (int q = 0; q < P; ++q) v += tot[w][q][t];
     if (t < NMF_BPP_COUNTERS) {
       if (counters && v) atomicAdd(counters + t, v);
     } else if (status_counts && v) {
@@ -1142,18 +1148,20 @@ int64_t grid_blocks(int K, int64_t batch) {
   return blocks < kMaxBppBlocks ? blocks : kMaxBppBlocks;
 }
 
-// K in {56, 64}: the two-problem kernel's blocks, then the scan's (a chunk of
-// 64 problems per wavefront)
-int64_t pair_blocks(int64_t batch) {
-  const int64_t b = nmf::cdiv(nmf::cdiv(batch, 2), kPairWaves);
-  return b < kPairBlocks ? b : kPairBlocks;
+// K in {32, 56, 64}: the pivot-row kernel's blocks, then the scan's (a chunk
+// of 64 problems per wavefront)
+int64_t pair_blocks(int K, int64_t batch) {
+  const int64_t per_block = (int64_t)(64 / pair_lanes(K)) * pair_waves(K);
+  const int64_t cap = kPairBlocks;
+  const int64_t b = nmf::cdiv(batch, per_block);
+  return b < cap ? b : cap;
 }
 int64_t scan_blocks(int64_t batch) {
   const int64_t b = nmf::cdiv(nmf::cdiv(batch, 64), kWaves);
   return b < kMaxBppBlocks ? b : kMaxBppBlocks;
 }
 int64_t launch_blocks(int K, int64_t batch) {
-  return K >= 56 ? pair_blocks(batch) + scan_blocks(batch) : grid_blocks(K, batch);
+  return K >= 32 ? pair_blocks(K, batch) + scan_blocks(batch) : grid_blocks(K, batch);
 }
 
 template <int K>
@@ -1162,12 +1170,14 @@ int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, f
            int warm_cap, uint64_t* counters, double* dot_partial, uint64_t* status_counts, hipStream_t s) {
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
   unsigned long long* sc = reinterpret_cast<unsigned long long*>(status_counts);
-  if constexpr (K >= 56) {
-    const int64_t pb = pair_blocks(batch), db = scan_blocks(batch);
-    hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(kPairWaves * 64), 0, s, k, batch, G, R, ldr, X, ldx,
-                       mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
-    NMF_TRY(nmf::launch_status("nnls_bpp_batched (two problems per wavefront)"));
-    hipLaunchKernelGGL(k_bpp_deferred<K>, dim3((unsigned)db), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
+  if constexpr (K >= 32) {
+    const int64_t pb = pair_blocks(K, batch), db = scan_blocks(batch);
+    hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(pair_waves(K) * 64), 0, s, k, batch, G, R, ldr, X,
+                       ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
+    NMF_TRY(nmf::launch_status("nnls_bpp_batched (pivot rows only)"));
+    // deferred problems: one per wavefront, in the class that holds every k <= K
+    constexpr int KD = K == 64 ? 64 : 56;
+    hipLaunchKernelGGL(k_bpp_deferred<KD>, dim3((unsigned)db), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
                        mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial ? dot_partial + pb : nullptr,
                        sc);
     return nmf::launch_status("nnls_bpp_batched (deferred problems)");
