@@ -689,12 +689,12 @@ __device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __rest
 constexpr int kPairBlocks = 256;
 // wavefronts per block of the class KK (one block per CU for KK >= 56; two
 // for KK = 32, whose blocks are smaller in LDS)
-constexpr int pair_waves(int KK) { return 12; }
+constexpr int pair_waves(int KK) { return KK >= 56 ? 12 : 8; }
 // lanes per problem: indices h and h + L belong to lane h of a group
 constexpr int pair_lanes(int KK) { return KK >= 56 ? 32 : KK / 2; }
 
 template <int KK>
-__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(3))) void k_bpp_pair(int k, int64_t batch, const double* __restrict__ G,
+__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK >= 56 ? 3 : 4))) void k_bpp_pair(int k, int64_t batch, const double* __restrict__ G,
                                                    const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
                                                    int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
                                                    uint8_t* __restrict__ rounds_out, uint8_t* __restrict__ status_out,
@@ -710,22 +710,32 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
   constexpr int kPer = (KK * KK + NT - 1) / NT;  // sweep entries per thread
   __shared__ double Gs[KK * KK];
   __shared__ double Gi[KK * KK];
-  __shared__ double colv[NW][P][L];
-  __shared__ double rfv[NW][P][L + 1];
-  __shared__ double dgv[NW][P][L + 1];
-  __shared__ double vv[NW][P][2 * L];
-  __shared__ int pix[NW][P][L + 1];
-  // statistics in LDS (registers are the scarce resource here): per problem
-  // (solves, sum |F|, |F|^2, |F|^3, pivot steps) and per half-wavefront
-  // totals (the NMF_BPP_COUNTERS in order, then capped and fell-back counts)
-  __shared__ uint32_t pcnt[NW][P][5];
-  __shared__ unsigned long long tot[NW][P][NMF_BPP_COUNTERS + 2];
+  // one problem group's exchange arrays, in one block of LDS so that a
+  // single per-lane base address serves them all; statistics live here too
+  // (registers are the scarce resource): per problem (solves, sum |F|,
+  // |F|^2, |F|^3, pivot steps) and the group's totals (the
+  // NMF_BPP_COUNTERS in order, then capped and fell-back counts)
+  struct Grp {
+    double colv[L];
+    double rfv[L + 1];
+    double dgv[L + 1];
+    double vv[2 * L];
+    double fv[2 * L];  // the problem's right-hand side f
+    double zv[2 * L];  // z = G_U^{-1} f
+    double dotv[L];    // per lane: sum of f_i x_i over its finished problems
+    unsigned long long tot[NMF_BPP_COUNTERS + 2];
+    int pix[L + 1];
+    uint32_t pcnt[5];
+  };
+  __shared__ Grp grps[NW][P];
   __shared__ double dsum[NW];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int grp = lane / L, h = lane % L;
+  Grp& gs = grps[wave][grp];
   if (h == 0)
-    for (int e = 0; e < NMF_BPP_COUNTERS + 2; ++e) tot[wave][grp][e] = 0;
+    for (int e = 0; e < NMF_BPP_COUNTERS + 2; ++e) gs.tot[e] = 0;
+  gs.dotv[h] = 0.0;
   const int i0 = h, i1 = h + L;
   // LDS column of an owned index (indices >= KK exist only as padding lanes)
   const int c1 = i1 < KK ? i1 : KK - 1;
@@ -800,14 +810,13 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
     __syncthreads();
   }
 
-  double dot = 0.0;
-  uint32_t* pc = &pcnt[wave][grp][0];
-  unsigned long long* tg = &tot[wave][grp][0];
-  int* pw = &pix[wave][grp][0];
-  double* colw = &colv[wave][grp][0];
-  double* rfw = &rfv[wave][grp][0];
-  double* dgw = &dgv[wave][grp][0];
-  double* vw = &vv[wave][grp][0];
+  uint32_t* pc = gs.pcnt;
+  unsigned long long* tg = gs.tot;
+  int* pw = gs.pix;
+  double* colw = gs.colv;
+  double* rfw = gs.rfv;
+  double* dgw = gs.dgv;
+  double* vw = gs.vv;
 
   const int64_t npair = (batch + P - 1) / P;  // problem groups, one per wavefront
   const int64_t gstride = (int64_t)gridDim.x * NW;
@@ -826,7 +835,10 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
     const int64_t b = P * g + grp;
     const bool vprob = b < batch;
     const bool val0 = vprob && i0 < k, val1 = vprob && i1 < k;
-    const double f0 = (double)fn0, f1 = (double)fn1;
+    double* fw = gs.fv;
+    double* zw = gs.zv;
+    fw[i0] = (double)fn0;
+    fw[i1] = (double)fn1;
     uint64_t F = vprob ? (mn & all & ~pinned0) : 0ull;
     {
       const int64_t bn = P * (g + gstride) + grp;
@@ -845,29 +857,30 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
       for (int e = 0; e < 5; ++e) pc[e] = 0;
     // stores a finished problem's x (as FP32) and its share of the dot sum
     auto finish = [&](double x0, double x1) {
+      double d = gs.dotv[h];
       if (val0) {
         const float xs = (float)x0;
         X[b * ldx + i0] = xs;
-        dot += (double)xs * f0;
+        d += (double)xs * fw[i0];
       }
       if (val1) {
         const float xs = (float)x1;
         X[b * ldx + i1] = xs;
-        dot += (double)xs * f1;
+        d += (double)xs * fw[i1];
       }
+      gs.dotv[h] = d;
     };
     // unconstrained solution z = G_U^{-1} f at the owned indices
-    double z0 = 0.0, z1 = 0.0;
+    wave_lds_sync();
     if (inv_ok) {
-      vw[i0] = f0;
-      vw[i1] = f1;
-      wave_lds_sync();
+      double z0 = 0.0, z1 = 0.0;
       for (int q = 0; q < k; ++q) {
-        const double fq = vw[q];
+        const double fq = fw[q];
         z0 += Gi[q * KK + i0] * fq;
         z1 += Gi[q * KK + c1] * fq;
       }
-      wave_lds_sync();
+      zw[i0] = z0;
+      zw[i1] = z1;
     }
 
     while (__ballot(!done) != 0) {
@@ -892,10 +905,10 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
       const int s0 = pv0 ? off + __popcll(Pv & (bit64(i0) - 1ull)) : L;
       const int s1 = pv1 ? off + __popcll(Pv & (bit64(i1) - 1ull)) : L;
       pw[s0] = i0;
-      rfw[s0] = useInv ? z0 : f0;
+      rfw[s0] = useInv ? zw[i0] : fw[i0];
       dgw[s0] = Mrow[i0 * KK + i0];
       pw[s1] = i1;
-      rfw[s1] = useInv ? z1 : f1;
+      rfw[s1] = useInv ? zw[i1] : fw[i1];
       dgw[s1] = Mrow[c1 * KK + c1];
       wave_lds_sync();
       const bool mine = h >= off && h < NP;
@@ -975,15 +988,15 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
       const bool pin0 = (pinned >> i0) & 1ull, pin1 = (pinned >> i1) & 1ull;
       double x0, y0, x1, y1;
       if (useInv) {
-        x0 = inF0 ? z0 - acc0 : 0.0;
+        x0 = inF0 ? zw[i0] - acc0 : 0.0;
         y0 = (inF0 || pin0) ? 0.0 : -own0;
-        x1 = inF1 ? z1 - acc1 : 0.0;
+        x1 = inF1 ? zw[i1] - acc1 : 0.0;
         y1 = (inF1 || pin1) ? 0.0 : -own1;
       } else {
         x0 = inF0 ? own0 : 0.0;
-        y0 = inF0 ? 0.0 : acc0 - f0;
+        y0 = inF0 ? 0.0 : acc0 - fw[i0];
         x1 = inF1 ? own1 : 0.0;
-        y1 = inF1 ? 0.0 : acc1 - f1;
+        y1 = inF1 ? 0.0 : acc1 - fw[i1];
       }
       const bool live = !done && !retry;
       const bool viol0 = val0 && live && !pin0 && (inF0 ? (x0 < 0.0) : (y0 < 0.0));
@@ -1053,6 +1066,7 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
     }
   }
   // block sums: the dot partial in a fixed order, the counts by atomics
+  double dot = gs.dotv[h];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o, 64);
   if (lane == 0) dsum[wave] = dot;
@@ -1065,7 +1079,7 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
   if (t < NMF_BPP_COUNTERS + 2) {
     unsigned long long v = 0;
     for (int w = 0; w < NW; ++w)
-      for (int q = 0; q < P; ++q) v += tot[w][q][t];
+      for (int q = 0; q < P; ++q) v += grps[w][q].tot[t];
     if (t < NMF_BPP_COUNTERS) {
       if (counters && v) atomicAdd(counters + t, v);
     } else if (status_counts && v) {
@@ -1152,7 +1166,7 @@ int64_t grid_blocks(int K, int64_t batch) {
 // of 64 problems per wavefront)
 int64_t pair_blocks(int K, int64_t batch) {
   const int64_t per_block = (int64_t)(64 / pair_lanes(K)) * pair_waves(K);
-  const int64_t cap = kPairBlocks;
+  const int64_t cap = K >= 56 ? kPairBlocks : 2 * kPairBlocks;
   const int64_t b = nmf::cdiv(batch, per_block);
   return b < cap ? b : cap;
 }
