@@ -693,28 +693,15 @@ constexpr int pair_waves(int KK) { return KK >= 56 ? 12 : 8; }
 // lanes per problem: indices h and h + L belong to lane h of a group
 constexpr int pair_lanes(int KK) { return KK >= 56 ? 32 : KK / 2; }
 
+// LDS of a pivot-row block: G and G_U^{-1}, and per problem group its
+// exchange arrays, right-hand side, unconstrained solution and statistics in
+// one struct, so that a single per-lane base address serves them all (and f,
+// z and the statistics need no registers, the scarce resource here).
 template <int KK>
-__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK >= 56 ? 3 : 4))) void k_bpp_pair(int k, int64_t batch, const double* __restrict__ G,
-                                                   const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
-                                                   int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
-                                                   uint8_t* __restrict__ rounds_out, uint8_t* __restrict__ status_out,
-                                                   int max_rounds, int warm_cap,
-                                                   unsigned long long* __restrict__ counters,
-                                                   double* __restrict__ dot_partial,
-                                                   unsigned long long* __restrict__ status_counts) {
-  constexpr int L = pair_lanes(KK);  // lanes per problem
-  constexpr int P = 64 / L;          // problems per wavefront
-  constexpr int NP = KK / 2;         // pivot positions: k <= KK, so at most KK / 2 pivots
-  constexpr int NW = pair_waves(KK);
-  constexpr int NT = NW * 64;
-  constexpr int kPer = (KK * KK + NT - 1) / NT;  // sweep entries per thread
-  __shared__ double Gs[KK * KK];
-  __shared__ double Gi[KK * KK];
-  // one problem group's exchange arrays, in one block of LDS so that a
-  // single per-lane base address serves them all; statistics live here too
-  // (registers are the scarce resource): per problem (solves, sum |F|,
-  // |F|^2, |F|^3, pivot steps) and the group's totals (the
-  // NMF_BPP_COUNTERS in order, then capped and fell-back counts)
+struct PairShared {
+  static constexpr int L = pair_lanes(KK);
+  static constexpr int P = 64 / L;
+  static constexpr int NW = pair_waves(KK);
   struct Grp {
     double colv[L];
     double rfv[L + 1];
@@ -723,23 +710,84 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
     double fv[2 * L];  // the problem's right-hand side f
     double zv[2 * L];  // z = G_U^{-1} f
     double dotv[L];    // per lane: sum of f_i x_i over its finished problems
+    // the group's totals: the NMF_BPP_COUNTERS in order, then the capped and
+    // fell-back counts
     unsigned long long tot[NMF_BPP_COUNTERS + 2];
     int pix[L + 1];
-    uint32_t pcnt[5];
+    uint32_t pcnt[5];  // this problem's solves, sum |F|, |F|^2, |F|^3, pivot steps
   };
-  __shared__ Grp grps[NW][P];
-  __shared__ double dsum[NW];
+  double Gs[KK * KK];
+  double Gi[KK * KK];
+  Grp grps[NW][P];
+  double dsum[NW];
 
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __device__ void clear_stats() {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    Grp& gs = grps[wave][lane / L];
+    if (lane % L == 0)
+      for (int e = 0; e < NMF_BPP_COUNTERS + 2; ++e) gs.tot[e] = 0;
+    gs.dotv[lane % L] = 0.0;
+  }
+  // block sums: the dot partial in a fixed order, the counts by atomics
+  __device__ void flush(unsigned long long* counters, double* dot_partial, unsigned long long* status_counts) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double dot = grps[wave][lane / L].dotv[lane % L];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o, 64);
+    if (lane == 0) dsum[wave] = dot;
+    __syncthreads();
+    if (t == 0 && dot_partial) {
+      double bd = 0.0;
+      for (int w = 0; w < NW; ++w) bd += dsum[w];
+      dot_partial[blockIdx.x] = bd;
+    }
+    if (t < NMF_BPP_COUNTERS + 2) {
+      unsigned long long v = 0;
+      for (int w = 0; w < NW; ++w)
+        for (int q = 0; q < P; ++q) v += grps[w][q].tot[t];
+      if (t < NMF_BPP_COUNTERS) {
+        if (counters && v) atomicAdd(counters + t, v);
+      } else if (status_counts && v) {
+        atomicAdd(status_counts + (t - NMF_BPP_COUNTERS), v);
+      }
+    }
+  }
+};
+
+// Solves problems [b0, b1) of one G: problem group g (P problems, one per
+// L lanes) for g = g_first, g_first + g_step, ...  Loads G and runs the sweep
+// first (after a barrier, so a persistent loop may call it again with
+// another G); adds its statistics to sh.
+template <int KK>
+__device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const double* __restrict__ G,
+                                           const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
+                                           int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
+                                           uint8_t* __restrict__ rounds_out, uint8_t* __restrict__ status_out,
+                                           int max_rounds, int warm_cap, int64_t b0, int64_t b1, int64_t g_first,
+                                           int64_t g_step) {
+  constexpr int L = pair_lanes(KK);  // lanes per problem
+  constexpr int P = 64 / L;          // problems per wavefront
+  constexpr int NP = KK / 2;         // pivot positions: k <= KK, so at most KK / 2 pivots
+  constexpr int NW = pair_waves(KK);
+  constexpr int NT = NW * 64;
+  constexpr int kPer = (KK * KK + NT - 1) / NT;  // sweep entries per thread
+  using Grp = typename PairShared<KK>::Grp;
+  double* Gs = sh.Gs;
+  double* Gi = sh.Gi;
+
+  // the thread index through an opaque copy: a persistent caller would
+  // otherwise have the sweep's per-thread addresses hoisted out of its item
+  // loop and kept alive through every solve
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  const int lane = t & 63, wave = t >> 6;
   const int grp = lane / L, h = lane % L;
-  Grp& gs = grps[wave][grp];
-  if (h == 0)
-    for (int e = 0; e < NMF_BPP_COUNTERS + 2; ++e) gs.tot[e] = 0;
-  gs.dotv[h] = 0.0;
+  Grp& gs = sh.grps[wave][grp];
   const int i0 = h, i1 = h + L;
   // LDS column of an owned index (indices >= KK exist only as padding lanes)
   const int c1 = i1 < KK ? i1 : KK - 1;
 
+  __syncthreads();
   for (int idx = t; idx < KK * KK; idx += NT) {
     const int q = idx / KK, pp = idx - q * KK;
     const double v = (q < k && pp < k) ? G[q * k + pp] : (q == pp ? 1.0 : 0.0);
@@ -818,22 +866,22 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
   double* dgw = gs.dgv;
   double* vw = gs.vv;
 
-  const int64_t npair = (batch + P - 1) / P;  // problem groups, one per wavefront
-  const int64_t gstride = (int64_t)gridDim.x * NW;
-  int64_t g = (int64_t)blockIdx.x * NW + wave;
+  const int64_t npair = (b1 - b0 + P - 1) / P;  // problem groups, one per wavefront
+  const int64_t gstride = g_step;
+  int64_t g = g_first;
   float fn0 = 0.0f, fn1 = 0.0f;
   uint64_t mn = 0;
   {
-    const int64_t b = P * g + grp;
-    if (g < npair && b < batch) {
+    const int64_t b = b0 + P * g + grp;
+    if (g < npair && b < b1) {
       if (i0 < k) fn0 = R[b * ldr + i0];
       if (i1 < k) fn1 = R[b * ldr + i1];
       if (mask_in) mn = mask_in[b];
     }
   }
   for (; g < npair; g += gstride) {
-    const int64_t b = P * g + grp;
-    const bool vprob = b < batch;
+    const int64_t b = b0 + P * g + grp;
+    const bool vprob = b < b1;
     const bool val0 = vprob && i0 < k, val1 = vprob && i1 < k;
     double* fw = gs.fv;
     double* zw = gs.zv;
@@ -841,8 +889,8 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
     fw[i1] = (double)fn1;
     uint64_t F = vprob ? (mn & all & ~pinned0) : 0ull;
     {
-      const int64_t bn = P * (g + gstride) + grp;
-      const bool vn = g + gstride < npair && bn < batch;
+      const int64_t bn = b0 + P * (g + gstride) + grp;
+      const bool vn = g + gstride < npair && bn < b1;
       fn0 = (vn && i0 < k) ? R[bn * ldr + i0] : 0.0f;
       fn1 = (vn && i1 < k) ? R[bn * ldr + i1] : 0.0f;
       mn = (vn && mask_in) ? mask_in[bn] : 0ull;
@@ -917,8 +965,12 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
         if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
-        // positions before the pivots are never read; they load row 0
-        const int jc = c >= off ? pw[c] : 0;
+        // positions before the pivots are never read; they load row 0.  (The
+        // position tests of the three loops use an opaque copy of c, so the
+        // compiler does not keep NP lane masks alive through the round.)
+        int cs = c;
+        asm volatile("" : "+s"(cs));
+        const int jc = cs >= off ? pw[c] : 0;
         r[c] = Mrow[jc * KK + jh];
       }
       double rf = mine ? rfw[h] : 0.0, mypiv = 1.0;
@@ -926,13 +978,11 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
       wave_lds_sync();
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
-        if (__ballot(c >= off) == 0ull) continue;
-        const bool act = c >= off;
-        // this step's pivot lane, tested here (an opaque copy of c keeps the
-        // compiler from holding 32 precomputed lane masks through the loop)
         int cs = c;
         asm volatile("" : "+s"(cs));
-        const bool pl = h == cs;
+        const bool act = cs >= off;
+        if (__ballot(act) == 0ull) continue;
+        const bool pl = h == cs;  // this step's pivot lane
         colw[h] = r[c];
         rfw[h] = rf;
         wave_lds_sync();
@@ -975,9 +1025,12 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
       double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
-        if (__ballot(c >= off) == 0ull) continue;
+        int cs = c;
+        asm volatile("" : "+s"(cs));
+        const bool act = cs >= off;
+        if (__ballot(act) == 0ull) continue;
         if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
-        const int jc = c >= off ? pw[c] : 0;
+        const int jc = act ? pw[c] : 0;
         const double vc = vw[c];
         acc0 += Mrow[jc * KK + i0] * vc;
         acc1 += Mrow[jc * KK + c1] * vc;
@@ -1065,27 +1118,37 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
       }
     }
   }
-  // block sums: the dot partial in a fixed order, the counts by atomics
-  double dot = gs.dotv[h];
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o, 64);
-  if (lane == 0) dsum[wave] = dot;
-  __syncthreads();
-  if (t == 0) {
-    double bd = 0.0;
-    for (int w = 0; w < NW; ++w) bd += dsum[w];
-    if (dot_partial) dot_partial[blockIdx.x] = bd;
+}
+
+template <int KK>
+__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK >= 56 ? 3 : 4))) void k_bpp_pair(
+    int k, int64_t batch, const double* __restrict__ G, const float* __restrict__ R, int64_t ldr,
+    float* __restrict__ X, int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
+    uint8_t* __restrict__ status_out, int max_rounds, int warm_cap, unsigned long long* __restrict__ counters,
+    double* __restrict__ dot_partial, unsigned long long* __restrict__ status_counts) {
+  __shared__ PairShared<KK> sh;
+  constexpr int NW = pair_waves(KK);
+  sh.clear_stats();
+  pair_block<KK>(sh, k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0, batch,
+                 (int64_t)blockIdx.x * NW + (threadIdx.x >> 6), (int64_t)gridDim.x * NW);
+  sh.flush(counters, dot_partial, status_counts);
+}
+
+// Grouped form: a persistent walk over items (ranges of problems of one G),
+// each block taking whole items.
+template <int KK>
+__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK >= 56 ? 3 : 4))) void
+k_bpp_pair_grouped(const nmf::BppItem* __restrict__ items, int64_t n, int max_rounds, int warm_cap,
+                   unsigned long long* __restrict__ counters) {
+  __shared__ PairShared<KK> sh;
+  constexpr int NW = pair_waves(KK);
+  sh.clear_stats();
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::BppItem it = items[i];
+    pair_block<KK>(sh, it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status, max_rounds,
+                   warm_cap, it.b0, it.b1, threadIdx.x >> 6, NW);
   }
-  if (t < NMF_BPP_COUNTERS + 2) {
-    unsigned long long v = 0;
-    for (int w = 0; w < NW; ++w)
-      for (int q = 0; q < P; ++q) v += grps[w][q].tot[t];
-    if (t < NMF_BPP_COUNTERS) {
-      if (counters && v) atomicAdd(counters + t, v);
-    } else if (status_counts && v) {
-      atomicAdd(status_counts + (t - NMF_BPP_COUNTERS), v);
-    }
-  }
+  sh.flush(counters, nullptr, nullptr);
 }
 
 // The one-problem kernel's scan form: solves the problems that k_bpp_pair
@@ -1134,6 +1197,29 @@ __global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double*
                         batch, (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves, cacc, ex);
   if (counters) flush_counters(cacc, counters);
   if (dot_partial || status_counts) flush_extras(ex, dot_partial, status_counts);
+}
+
+// Grouped scan form: for each item with marked problems, the one-problem
+// kernel solves them (items without marks are skipped before G is loaded).
+template <int K>
+__global__ __launch_bounds__(256) void k_bpp_deferred_grouped(const nmf::BppItem* __restrict__ items, int64_t n,
+                                                              int max_rounds, int warm_cap,
+                                                              unsigned long long* __restrict__ counters) {
+  unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
+  BppExtras ex;  // not used here
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const nmf::BppItem it = items[i];
+    bool any = false;
+    for (int64_t c0 = it.b0 + wave * 64; c0 < it.b1; c0 += kWaves * 64) {
+      const int64_t bb = c0 + lane;
+      any |= bb < it.b1 && __float_as_uint(it.X[bb * it.ldx]) == kDeferMark;
+    }
+    if (!__syncthreads_or(any)) continue;
+    bpp_block<K, false, true>(it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status,
+                              max_rounds, warm_cap, it.b0, it.b1, wave, kWaves, cacc, ex);
+  }
+  if (counters) flush_counters(cacc, counters);
 }
 
 // Grouped form: a persistent walk over items, each a range of problems of
@@ -1224,6 +1310,22 @@ int bpp_launch(int k, int64_t batch, const double* G, const float* R, int64_t ld
 #undef NMF_BPP_LAUNCH
 }
 
+// The pivot-row classes: the grouped kernel, then the scan of its deferred
+// problems (grid of the scan: one block per item up to the pivot-row grid's
+// wavefront count).
+template <int K>
+int pair_grouped_launch(const BppItem* items, int64_t n, int grid, int max_rounds, int warm_cap,
+                        unsigned long long* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_bpp_pair_grouped<K>, dim3((unsigned)grid), dim3(pair_waves(K) * 64), 0, s, items, n,
+                     max_rounds, warm_cap, c);
+  NMF_TRY(launch_status("nnls bpp (grouped, pivot rows only)"));
+  constexpr int KD = K == 64 ? 64 : 56;
+  const int64_t sg = n < (int64_t)grid * pair_waves(K) ? n : (int64_t)grid * pair_waves(K);
+  hipLaunchKernelGGL(k_bpp_deferred_grouped<KD>, dim3((unsigned)sg), dim3(256), 0, s, items, n, max_rounds, warm_cap,
+                     c);
+  return launch_status("nnls bpp (grouped, deferred problems)");
+}
+
 int bpp_grouped_launch(int K, const BppItem* items, int64_t n, int grid, int max_rounds, int warm_cap,
                        uint64_t* counters, hipStream_t s) {
   if (n == 0) return NMF_OK;
@@ -1231,9 +1333,9 @@ int bpp_grouped_launch(int K, const BppItem* items, int64_t n, int grid, int max
   switch (K) {
     case 8: hipLaunchKernelGGL(k_bpp_grouped<8>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
     case 16: hipLaunchKernelGGL(k_bpp_grouped<16>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
-    case 32: hipLaunchKernelGGL(k_bpp_grouped<32>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
-    case 56: hipLaunchKernelGGL(k_bpp_grouped<56>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
-    case 64: hipLaunchKernelGGL(k_bpp_grouped<64>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
+    case 32: return pair_grouped_launch<32>(items, n, grid, max_rounds, warm_cap, c, s);
+    case 56: return pair_grouped_launch<56>(items, n, grid, max_rounds, warm_cap, c, s);
+    case 64: return pair_grouped_launch<64>(items, n, grid, max_rounds, warm_cap, c, s);
     default: return fail(NMF_EINVAL, "bpp (grouped): K=%d", K);
   }
   return launch_status("nnls bpp (grouped)");
@@ -1246,9 +1348,9 @@ int bpp_grouped_occupancy(int K, int* per_cu) {
   switch (K) {
     case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<8>, 256, 0); break;
     case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<16>, 256, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<32>, 256, 0); break;
-    case 56: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<56>, 256, 0); break;
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<64>, 256, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<32>, pair_waves(32) * 64, 0); break;
+    case 56: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<56>, pair_waves(56) * 64, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<64>, pair_waves(64) * 64, 0); break;
     default: break;
   }
   return e == hipSuccess ? NMF_OK : NMF_EHIP;
