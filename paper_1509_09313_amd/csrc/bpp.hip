@@ -716,8 +716,12 @@ struct PairShared {
     int pix[L + 1];
     uint32_t pcnt[5];  // this problem's solves, sum |F|, |F|^2, |F|^3, pivot steps
   };
-  double Gs[KK * KK];
-  double Gi[KK * KK];
+  // row stride of G and G_U^{-1}: one more than KK, so that the problem
+  // groups of a wavefront, reading different rows at the same columns, do
+  // not meet in one LDS bank
+  static constexpr int KS = KK + 1;
+  double Gs[KK * KS];
+  double Gi[KK * KS];
   Grp grps[NW][P];
   double dsum[NW];
 
@@ -772,6 +776,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
   constexpr int NT = NW * 64;
   constexpr int kPer = (KK * KK + NT - 1) / NT;  // sweep entries per thread
   using Grp = typename PairShared<KK>::Grp;
+  constexpr int KS = PairShared<KK>::KS;
   double* Gs = sh.Gs;
   double* Gi = sh.Gi;
 
@@ -791,16 +796,16 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
   for (int idx = t; idx < KK * KK; idx += NT) {
     const int q = idx / KK, pp = idx - q * KK;
     const double v = (q < k && pp < k) ? G[q * k + pp] : (q == pp ? 1.0 : 0.0);
-    Gs[idx] = v;
-    Gi[idx] = v;
+    Gs[q * KS + pp] = v;
+    Gi[q * KS + pp] = v;
   }
   __syncthreads();
   const uint64_t all = (k == 64) ? ~0ull : (bit64(k) - 1ull);
   double dmax = 0.0;
-  for (int q = 0; q < k; ++q) dmax = fmax(dmax, Gs[q * KK + q]);
+  for (int q = 0; q < k; ++q) dmax = fmax(dmax, Gs[q * KS + q]);
   uint64_t pinned0 = 0;
   for (int q = 0; q < k; ++q)
-    if (Gs[q * KK + q] <= 1e-14 * dmax) pinned0 |= bit64(q);
+    if (Gs[q * KS + q] <= 1e-14 * dmax) pinned0 |= bit64(q);
 
   // G_U^{-1} by the symmetric sweep over the unpinned indices in index order,
   // on a row-major working copy W (row i in W[i][.]): sweeping j maps
@@ -810,8 +815,8 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
   bool inv_ok = true;
   for (int j = 0; j < k; ++j) {
     if ((pinned0 >> j) & 1ull) continue;
-    const double d = Gi[j * KK + j];
-    if (!(d > 1e-6 * Gs[j * KK + j])) inv_ok = false;
+    const double d = Gi[j * KS + j];
+    if (!(d > 1e-6 * Gs[j * KS + j])) inv_ok = false;
     const double inv = 1.0 / d;
     double nv[kPer];
 #pragma unroll
@@ -820,7 +825,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       nv[e] = 0.0;
       if (idx < KK * KK) {
         const int i = idx / KK, l = idx - i * KK;
-        const double wil = Gi[idx], wij = Gi[i * KK + j], wlj = Gi[l * KK + j];
+        const double wil = Gi[i * KS + l], wij = Gi[i * KS + j], wlj = Gi[l * KS + j];
         if (i == j) {
           nv[e] = l == j ? -inv : wil * inv;
         } else {
@@ -833,7 +838,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int idx = t + e * NT;
-      if (idx < KK * KK) Gi[idx] = nv[e];
+      if (idx < KK * KK) Gi[(idx / KK) * KS + idx % KK] = nv[e];
     }
     __syncthreads();
   }
@@ -846,14 +851,14 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       if (idx < KK * KK) {
         const int q = idx / KK, pl = idx - q * KK;
         const bool inU = q < k && pl < k && !((pinned0 >> q) & 1ull) && !((pinned0 >> pl) & 1ull);
-        nv[e] = inU ? -Gi[pl * KK + q] : 0.0;
+        nv[e] = inU ? -Gi[pl * KS + q] : 0.0;
       }
     }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int idx = t + e * NT;
-      if (idx < KK * KK) Gi[idx] = nv[e];
+      if (idx < KK * KK) Gi[(idx / KK) * KS + idx % KK] = nv[e];
     }
     __syncthreads();
   }
@@ -924,8 +929,8 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       double z0 = 0.0, z1 = 0.0;
       for (int q = 0; q < k; ++q) {
         const double fq = fw[q];
-        z0 += Gi[q * KK + i0] * fq;
-        z1 += Gi[q * KK + c1] * fq;
+        z0 += Gi[q * KS + i0] * fq;
+        z1 += Gi[q * KS + c1] * fq;
       }
       zw[i0] = z0;
       zw[i1] = z1;
@@ -954,10 +959,10 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       const int s1 = pv1 ? off + __popcll(Pv & (bit64(i1) - 1ull)) : L;
       pw[s0] = i0;
       rfw[s0] = useInv ? zw[i0] : fw[i0];
-      dgw[s0] = Mrow[i0 * KK + i0];
+      dgw[s0] = Mrow[i0 * KS + i0];
       pw[s1] = i1;
       rfw[s1] = useInv ? zw[i1] : fw[i1];
-      dgw[s1] = Mrow[c1 * KK + c1];
+      dgw[s1] = Mrow[c1 * KS + c1];
       wave_lds_sync();
       const bool mine = h >= off && h < NP;
       const int jh = mine ? pw[h] : 0;
@@ -970,8 +975,15 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
         // compiler does not keep NP lane masks alive through the round.)
         int cs = c;
         asm volatile("" : "+s"(cs));
-        const int jc = cs >= off ? pw[c] : 0;
-        r[c] = Mrow[jc * KK + jh];
+        const bool act = cs >= off;
+        // positions before every problem's first pivot are skipped (zero, so
+        // that no value is carried between rounds)
+        if (__ballot(act) == 0ull) {
+          r[c] = 0.0;
+          continue;
+        }
+        const int jc = act ? pw[c] : 0;
+        r[c] = Mrow[jc * KS + jh];
       }
       double rf = mine ? rfw[h] : 0.0, mypiv = 1.0;
       bool myok = mine;
@@ -1032,8 +1044,8 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
         if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
         const int jc = act ? pw[c] : 0;
         const double vc = vw[c];
-        acc0 += Mrow[jc * KK + i0] * vc;
-        acc1 += Mrow[jc * KK + c1] * vc;
+        acc0 += Mrow[jc * KS + i0] * vc;
+        acc1 += Mrow[jc * KS + c1] * vc;
       }
       const double own0 = vw[s0 < L ? s0 : 0], own1 = vw[s1 < L ? s1 : 0];
       wave_lds_sync();
