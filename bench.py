@@ -1138,6 +1138,11 @@ def main():
         "products_mfma": products_mfma(ph_l, a.m, a.n, a.k, "bf16x3"),
         "plain_fp32": plain,
         "speedup_vs_plain_fp32": None if plain is None else value / plain["iters_per_s"],
+        # the same ratio in two factors: BF16x3 products alone (both forms from cold BPP starts) and
+        # the learned start alone (learned against cold, both with BF16x3 products)
+        "speedup_attribution": None if plain is None or not warm or "cold" not in warm else {
+            "bf16x3_products": warm["cold"]["iters_per_s"] / plain["iters_per_s"],
+            "learned_start": value / warm["cold"]["iters_per_s"]},
         "matched_objective": None if plain is None else (
             abs(r_learned - plain["final_r"]) <= 1e-5 if oracle_r is None
             else (abs(r_learned - oracle_r) <= 1e-5 and abs(plain["final_r"] - oracle_r) <= 1e-5)),
