@@ -333,6 +333,11 @@ class Bench:
         self.M.add_split()
         torch.cuda.synchronize()
         self.t_split = time.perf_counter() - t0
+        # the plain FP32 form keeps A^T resident too (as the BF16 planes do for BF16x3)
+        t0 = time.perf_counter()
+        self.M.add_transposed()
+        torch.cuda.synchronize()
+        self.t_transpose = time.perf_counter() - t0
         self.W = torch.empty_like(self.W0)
         self.Ht = torch.empty_like(self.Ht0)
         # learned form: collection buffers, networks, runners
@@ -739,7 +744,13 @@ def dense_workload(a, steps, warmup, with_cpu=True):
     res = {"workload": f"planted dense {m}x{n} (rank 50 U[0,1) factors + 0.01 U[0,1) noise), k={k}, {T} cold-BPP "
                        f"iterations per step from the seeded start; stands in for the paper's DSYN",
            "steps": steps, "warmup": warmup, "generate_s": t_gen}
+    t0 = time.perf_counter()
+    M.add_transposed()
+    torch.cuda.synchronize()
+    res["one_time_fp32_transpose_s"] = time.perf_counter() - t0
     res["fp32"] = form(L.NMF_F32, "fp32")
+    M.drop_transposed()  # room for the BF16 planes
+    torch.cuda.empty_cache()
     t0 = time.perf_counter()
     M.add_split()
     torch.cuda.synchronize()
@@ -976,6 +987,7 @@ def ksweep_mode(a):
     A = gen.video(seed, m, n)
     M = L.Matrix(dense=A)
     M.add_split()
+    M.add_transposed()  # the FP32 forms' resident A^T
     ref = None
     if os.path.exists(KSWEEP_GOLDEN) and (m, n) == (1_000_000, 2_400):
         with open(KSWEEP_GOLDEN) as fh:
@@ -1149,6 +1161,7 @@ def main():
         "bpp_solves_w_per_row_learned": float(np.mean([s["bpp_w"][1] for s in st_l[b.T1:]]) / a.m),
         "bpp_fallbacks_learned": int(sum(s["fallback"] for s in st_l)),
         "one_time_split_s": b.t_split,
+        "one_time_fp32_transpose_s": b.t_transpose,
         "roofline": roof,
         "cpu_baseline": cpu,
         "warm_starts": warm,

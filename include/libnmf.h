@@ -142,6 +142,16 @@ int nmf_rhs_dense(int side, int64_t m, int64_t n, int k, const float* A, int64_t
 size_t nmf_split_bf16_bytes(int64_t rows, int64_t cols, int transpose);
 int nmf_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, int transpose, void* out, void* stream);
 
+/* One-time FP32 transposed copy: out (cols x rows, leading dimension ldo >=
+ * rows) = X^T for X rows x cols (ldx >= cols), all device pointers; exact.
+ * Keeping both orientations of A resident is what the BF16 planes do for the
+ * BF16X3 form; this gives the FP32 form the same (nmf_matrix.At).  X and out
+ * may not overlap.  An empty matrix is a no-op.  NMF_EINVAL for negative
+ * sizes, or for a non-empty matrix with short leading dimensions or a null
+ * pointer. */
+int nmf_transpose_f32(int64_t rows, int64_t cols, const float* X, int64_t ldx, float* out, int64_t ldo,
+                      void* stream);
+
 /* ---- sparse right-hand side -----------------------------------------------
  * R (rows x k) = A_csr (rows x cols) * Y (cols x k, ldy >= k).  Pass CSR(A)
  * with Y = Ht for A H^T, CSR(A^T) with Y = W for (W^T A)^T.  rowptr int64
@@ -236,6 +246,11 @@ typedef struct nmf_matrix {
   int64_t lda;
   const void* A_bf16;       /* BF16X3 only: padded BF16 form of A   (nmf_split_bf16, transpose 0) */
   const void* At_bf16;      /* BF16X3 only: padded BF16 form of A^T (nmf_split_bf16, transpose 1) */
+  const float* At;          /* FP32 only, optional: A^T (n x m, leading dimension ldat >= m, from
+                               nmf_transpose_f32); when set, nmf_anls_iter forms the side-H
+                               right-hand side A^T W as nmf_rhs_dense side W of A^T, whose
+                               row-streaming kernel reads the resident copy */
+  int64_t ldat;
   /* sparse */
   int64_t nnz;              /* number of stored entries (both CSR copies) */
   const int64_t* rowptr;    /* CSR(A):   m + 1 */

@@ -42,6 +42,7 @@ class nmf_matrix(ctypes.Structure):
     _fields_ = [("kind", ci), ("m", i64), ("n", i64),
                 ("A", vp), ("lda", i64),
                 ("A_bf16", vp), ("At_bf16", vp),
+                ("At", vp), ("ldat", i64),
                 ("nnz", i64),
                 ("rowptr", vp), ("colidx", vp), ("vals", vp),
                 ("rowptr_t", vp), ("colidx_t", vp), ("vals_t", vp),
@@ -105,6 +106,7 @@ def lib():
             "nmf_rhs_dense": ([ci, i64, i64, ci, vp, i64, vp, vp, i64, vp, i64, ci, vp, ctypes.c_size_t, vp], ci),
             "nmf_split_bf16_bytes": ([i64, i64, ci], ctypes.c_size_t),
             "nmf_split_bf16": ([i64, i64, vp, i64, ci, vp, vp], ci),
+            "nmf_transpose_f32": ([i64, i64, vp, i64, vp, i64, vp], ci),
             "nmf_rhs_csr": ([i64, i64, ci, vp, vp, vp, vp, i64, vp, i64, vp], ci),
             "nnls_bpp_batched": ([ci, i64, vp, vp, i64, vp, i64, vp, vp, vp, vp, ci, ci, vp, vp], ci),
             "nmf_local_update": ([ci, ci, i64, vp, vp, i64, vp, i64, vp], ci),
@@ -220,6 +222,15 @@ def nmf_split_bf16(X, transpose=False):
     return out
 
 
+def nmf_transpose_f32(X):
+    """X^T as a new contiguous FP32 device tensor (the library's transpose)."""
+    _dev(X, torch.float32, "X")
+    rows, cols = X.shape
+    out = torch.empty((cols, rows), dtype=torch.float32, device="cuda")
+    _check(lib().nmf_transpose_f32(rows, cols, _ptr(X), _ld(X), _ptr(out), rows, _stream()))
+    return out
+
+
 def unpack_bf16(buf, rows, cols):
     """Host helper for tests: (hi, lo) uint16 arrays (rows x cols) of the
     padded BF16 form of an operand with `rows` rows and `cols` columns."""
@@ -328,6 +339,22 @@ class Matrix:
         self.keep += [bt, btt]
         self.tiled = (bt, btt)
         self.s.A_bf16, self.s.At_bf16 = bt.data_ptr(), btt.data_ptr()
+
+    def add_transposed(self):
+        """The FP32 form's second orientation: a resident copy of A^T, which
+        nmf_anls_iter's side-H product then streams by rows."""
+        at = nmf_transpose_f32(self.A)
+        self.keep.append(at)
+        self.At = at
+        self.s.At, self.s.ldat = at.data_ptr(), _ld(at)
+
+    def drop_transposed(self):
+        """Releases the resident A^T (the FP32 side-H product then streams A)."""
+        at = getattr(self, "At", None)
+        if at is not None:
+            self.keep = [t for t in self.keep if t is not at]
+            self.At = None
+            self.s.At, self.s.ldat = None, 0
 
     def ref(self):
         return ctypes.byref(self.s)

@@ -87,7 +87,10 @@ int plan_anls(const nmf_matrix* A, int k, const nmf_opts* o, nmf::Carver& c, Pla
   P->rhs_w = P->rhs_h = nullptr;
   if (A->kind == NMF_DENSE) {
     NMF_TRY(nmf::rhs_dense_plan(NMF_SIDE_W, m, n, k, o->prec, c, &P->rhs_w));
-    NMF_TRY(nmf::rhs_dense_plan(NMF_SIDE_H, m, n, k, o->prec, c, &P->rhs_h));
+    if (o->prec == NMF_F32 && A->At)
+      NMF_TRY(nmf::rhs_dense_plan(NMF_SIDE_W, n, m, k, o->prec, c, &P->rhs_h));  // A^T W as side W of A^T
+    else
+      NMF_TRY(nmf::rhs_dense_plan(NMF_SIDE_H, m, n, k, o->prec, c, &P->rhs_h));
   } else if (nmf::csr_pad_ld(k) != k) {
     // line-aligned copy of the SpMM's factor (Ht, then W: one after the other)
     P->rhs_w = P->rhs_h = c.take<float>((size_t)mx * nmf::csr_pad_ld(k));
@@ -134,6 +137,7 @@ int check_matrix(const nmf_matrix* A) {
   if (A->m < 1 || A->n < 1) return nmf::fail(NMF_EINVAL, "nmf_anls: empty matrix");
   if (A->kind == NMF_DENSE) {
     if (A->lda < A->n || !A->A) return nmf::fail(NMF_EINVAL, "nmf_anls: bad dense matrix");
+    if (A->At && A->ldat < A->m) return nmf::fail(NMF_EINVAL, "nmf_anls: ldat < m");
   } else if (A->kind == NMF_CSR) {
     if (!A->rowptr || !A->colidx || !A->vals || !A->rowptr_t || !A->colidx_t || !A->vals_t)
       return nmf::fail(NMF_EINVAL, "nmf_anls: CSR(A) and CSR(A^T) are both needed");
@@ -151,6 +155,8 @@ int rhs(const nmf_matrix* A, int side, int k, int prec, const float* Y, float* R
       return nmf::rhs_csr_launch(A->m, A->n, k, A->rowptr, A->colidx, A->vals, Y, k, R, k, ypad, s);
     return nmf::rhs_csr_launch(A->n, A->m, k, A->rowptr_t, A->colidx_t, A->vals_t, Y, k, R, k, ypad, s);
   }
+  if (side == NMF_SIDE_H && prec == NMF_F32 && A->At)  // the resident A^T: A^T W streams its rows
+    return nmf::rhs_dense_launch(NMF_SIDE_W, A->n, A->m, k, A->At, A->ldat, nullptr, Y, k, R, k, prec, scratch, s);
   const void* bt = side == NMF_SIDE_W ? A->A_bf16 : A->At_bf16;
   return nmf::rhs_dense_launch(side, A->m, A->n, k, A->A, A->lda, bt, Y, k, R, k, prec, scratch, s, y_ready);
 }

@@ -10,7 +10,10 @@
 // operand comes from one 16-byte load.
 //   side W stages 128 x 32 tiles of A and of the transposed Y in LDS (rows of
 //     A are contracted along their contiguous dimension, so lanes need
-//     different rows), two chunks in flight;
+//     different rows), two chunks in flight; when A has too few row tiles to
+//     fill the device (A^T of a tall matrix: Ht = A^T W over a resident FP32
+//     A^T), the contraction is split into S column ranges whose FP32
+//     partials are summed in FP64 in a fixed order;
 //   side H needs no LDS: lane (j, h) loads A[r + h][c0 + 4j .. +3] with one
 //     16-byte load (a 512-byte contiguous segment per half-wave) and feeds
 //     four MFMAs, one per component, with the next rows' loads issued before
@@ -157,10 +160,20 @@ constexpr int kSPitch = kSC + 4;   // LDS pitch in floats (== 4 mod 32: conflict
 constexpr int kSRowsPass = 256 / (kSC / 4);  // rows one staging pass covers
 constexpr int kSPassA = kWTM / kSRowsPass;   // passes over the 128-row A tile
 
+// blockIdx.y = s takes contraction columns [s cps, (s + 1) cps) and writes
+// its product to R + s pstride (a single range: cps >= n, pstride 0).
 template <int NT>
 __global__ __launch_bounds__(256) void k_rhs_w_f32s(int64_t m, int64_t n, int k, const float* __restrict__ A,
                                                     int64_t lda, const float* __restrict__ Yt, int64_t ldt,
-                                                    float* __restrict__ R, int64_t ldr) {
+                                                    float* __restrict__ R, int64_t ldr, int64_t cps,
+                                                    int64_t pstride) {
+  {
+    const int64_t cs0 = (int64_t)blockIdx.y * cps;
+    A += cs0;
+    Yt += cs0;
+    n = n - cs0 < cps ? n - cs0 : cps;
+    R += (int64_t)blockIdx.y * pstride;
+  }
   constexpr int KP = 32 * NT;
   constexpr int kPassY = KP / kSRowsPass;
   __shared__ __align__(16) float As[kWTM * kSPitch];
@@ -543,18 +556,72 @@ int64_t w_yt_ld(int64_t n) { return nmf::cdiv(n, 64) * 64; }
 
 bool w_streaming(const float* A, int64_t lda) { return (lda % 4 == 0) && ((uintptr_t)A % 16 == 0); }
 
+// Contraction split of the streaming side-W kernel: as many column ranges as
+// fit row tiles x ranges into kWSplitBlocks workgroups (three resident per CU
+// on 256 CUs: one whole round, since a second partial round of these
+// long-lived workgroups would nearly double the time), each range at least
+// kWSplitMinChunks chunks long.
+constexpr int64_t kWSplitBlocks = 768;
+constexpr int64_t kWSplitMinChunks = 64;
+struct WSplit {
+  int S;
+  int64_t cps;  // columns per range, a multiple of the chunk
+};
+WSplit w_split(int64_t m, int64_t n) {
+  const int64_t tiles = nmf::cdiv(m, kWTM);
+  int64_t S = tiles > 0 ? kWSplitBlocks / tiles : 1;
+  if (S <= 1 && n >= 1024 * kSC) {
+    // at least a round of tiles and a long contraction: the split count up
+    // to 8 whose workgroups fill their last round best
+    double best = 0.0;
+    for (int64_t q = 1; q <= 8; ++q) {
+      const int64_t blocks = tiles * q;
+      const double fill = (double)blocks / (double)(nmf::cdiv(blocks, kWSplitBlocks) * kWSplitBlocks);
+      if (fill > best + 1e-9) {
+        best = fill;
+        S = q;
+      }
+    }
+  }
+  const int64_t max_s = n / (kWSplitMinChunks * kSC);
+  if (S > max_s) S = max_s;
+  if (S > 65535) S = 65535;
+  if (S < 1) S = 1;
+  int64_t cps = nmf::cdiv(nmf::cdiv(n, S), kSC) * kSC;
+  if (cps < kSC) cps = kSC;
+  WSplit w;
+  w.S = (int)nmf::cdiv(n, cps);
+  if (w.S < 1) w.S = 1;
+  w.cps = w.S > 1 ? cps : (n > 0 ? n : 1);
+  return w;
+}
+// floats of the side-W scratch: the transposed Y, then (split) the partials
+size_t w_yt_floats(int64_t n, int k) { return (size_t)(k <= 32 ? 32 : 64) * w_yt_ld(n); }
+
 template <int NT>
 int launch_w_f32(int64_t m, int64_t n, int k, const float* A, int64_t lda, const float* Y, int64_t ldy,
                  float* R, int64_t ldr, float* yt, hipStream_t s) {
   const dim3 grid((unsigned)nmf::cdiv(m, kWTM));
   if (w_streaming(A, lda)) {
     const int64_t ldt = w_yt_ld(n);
+    const WSplit sp = w_split(m, n);
+    float* partial = yt + w_yt_floats(n, k);
+    float* P = sp.S > 1 ? partial : R;
+    const int64_t ldp = sp.S > 1 ? k : ldr;
+    const int64_t stride = sp.S > 1 ? m * k : 0;
     hipLaunchKernelGGL(k_transpose_y, dim3((unsigned)(ldt / 64)), dim3(256), 0, s, n, k, 32 * NT, Y, ldy, yt, ldt);
     NMF_TRY(nmf::launch_status("rhs side W (fp32): transpose Y"));
     nmf::mark_begin(s);
-    hipLaunchKernelGGL((k_rhs_w_f32s<NT>), grid, dim3(256), 0, s, m, n, k, A, lda, yt, ldt, R, ldr);
+    hipLaunchKernelGGL((k_rhs_w_f32s<NT>), dim3(grid.x, (unsigned)sp.S), dim3(256), 0, s, m, n, k, A, lda, yt, ldt,
+                       P, ldp, sp.cps, stride);
     nmf::mark_end(s);
-    return nmf::launch_status("rhs side W (fp32)");
+    NMF_TRY(nmf::launch_status("rhs side W (fp32)"));
+    if (sp.S > 1) {
+      hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)nmf::cdiv(m * k, 256)), dim3(256), 0, s, m, k, sp.S, partial,
+                         stride, R, ldr);
+      NMF_TRY(nmf::launch_status("rhs side W reduce"));
+    }
+    return NMF_OK;
   }
   nmf::mark_begin(s);
   hipLaunchKernelGGL((k_rhs_w_f32<NT, false>), grid, dim3(256), 0, s, m, n, k, A, lda, Y, ldy, R, ldr);
@@ -607,8 +674,10 @@ int rhs_dense_plan(int side, int64_t m, int64_t n, int k, int prec, Carver& c, v
   *scratch = nullptr;
   if (prec == NMF_BF16X3) return bf16x3_plan(side, m, n, k, c, scratch);
   if (side == NMF_SIDE_W) {
-    // transposed, padded Y of the streaming kernel (whatever A's alignment)
-    *scratch = c.take<float>((size_t)(k <= 32 ? 32 : 64) * w_yt_ld(n));
+    // transposed, padded Y of the streaming kernel (whatever A's alignment),
+    // then the partials of a split contraction
+    const WSplit sp = w_split(m, n);
+    *scratch = c.take<float>(w_yt_floats(n, k) + (sp.S > 1 ? (size_t)sp.S * m * k : 0));
   } else {
     const HSplit sp = h_split(m, n);
     if (sp.S > 1) *scratch = c.take<float>((size_t)sp.S * n * k);
@@ -632,6 +701,40 @@ int rhs_dense_launch(int side, int64_t m, int64_t n, int k, const float* A, int6
 }
 
 }  // namespace nmf
+
+namespace {
+// out (cols x rows) = X^T through a 64 x 65 LDS tile (odd pitch: conflict-free
+// column reads); block (bx, by) takes rows 64 bx .. and columns 64 by ..
+__global__ __launch_bounds__(256) void k_transpose_f32(int64_t rows, int64_t cols, const float* __restrict__ X,
+                                                       int64_t ldx, float* __restrict__ out, int64_t ldo) {
+  __shared__ float tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < rows && c < cols) tile[i][tx] = X[r * ldx + c];
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols && r < rows) out[c * ldo + r] = tile[tx][i];
+  }
+}
+}  // namespace
+
+extern "C" int nmf_transpose_f32(int64_t rows, int64_t cols, const float* X, int64_t ldx, float* out, int64_t ldo,
+                                 void* stream) {
+  if (rows < 0 || cols < 0) return nmf::fail(NMF_EINVAL, "nmf_transpose_f32: negative size");
+  if (rows == 0 || cols == 0) return NMF_OK;  // nothing is read or written
+  if (ldx < cols || ldo < rows) return nmf::fail(NMF_EINVAL, "nmf_transpose_f32: short leading dimension");
+  if (!X || !out) return nmf::fail(NMF_EINVAL, "nmf_transpose_f32: null pointer");
+  const int64_t gx = nmf::cdiv(rows, 64), gy = nmf::cdiv(cols, 64);
+  if (gy > 65535 || gx > 0x7fffffff)
+    return nmf::fail(NMF_EINVAL, "nmf_transpose_f32: %lld x %lld exceeds the grid", (long long)rows, (long long)cols);
+  hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, nmf::as_stream(stream), rows,
+                     cols, X, ldx, out, ldo);
+  return nmf::launch_status("nmf_transpose_f32");
+}
 
 static int check_rhs_args(int side, int64_t m, int64_t n, int k, int prec, const float* A, int64_t lda,
                           const void* Bt, const float* Y, int64_t ldy, const float* R, int64_t ldr) {
@@ -660,7 +763,8 @@ extern "C" int nmf_rhs_dense_chain(int side, int64_t m, int64_t n, int k, int pr
   if (prec == NMF_BF16X3) {
     *terms = nmf::bf16x3_chain(side, m, n, k);
   } else if (side == NMF_SIDE_W) {
-    *terms = n;
+    const WSplit sp = w_split(m, n);
+    *terms = sp.S > 1 ? sp.cps : n;
   } else {
     const HSplit sp = h_split(m, n);
     *terms = sp.S > 1 ? sp.rows_per_split : m;

@@ -68,6 +68,12 @@ def test_host_validation_without_gpu(L):
     assert lib.nmf_rhs_dense(0, 4, 4, 2, z, 4, z, G, 2, G, 2, 1, G, 1 << 20, None) == L.NMF_EINVAL
     assert lib.nmf_split_bf16_bytes(300, 70, 0) == 2 * 384 * 128 * 2
     assert lib.nmf_split_bf16_bytes(300, 70, 1) == 2 * 128 * 320 * 2
+    # FP32 transpose: short leading dimensions, null pointers, empty matrices
+    assert lib.nmf_transpose_f32(4, 6, G, 5, G, 4, None) == L.NMF_EINVAL
+    assert lib.nmf_transpose_f32(4, 6, G, 6, G, 3, None) == L.NMF_EINVAL
+    assert lib.nmf_transpose_f32(4, 6, None, 6, G, 4, None) == L.NMF_EINVAL
+    assert lib.nmf_transpose_f32(-1, 6, G, 6, G, 4, None) == L.NMF_EINVAL
+    assert lib.nmf_transpose_f32(0, 6, None, 6, None, 0, None) == L.NMF_OK
     # CSR: ld < k
     assert lib.nmf_rhs_csr(4, 4, 8, G, G, G, G, 4, G, 8, None) == L.NMF_EINVAL
     # HALS / MU: bad solver, k, ld; ANLS with HALS takes no warm start
@@ -94,6 +100,13 @@ def test_host_validation_without_gpu(L):
     o = L.make_opts()
     assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_OK
     assert nb.value > 0
+    # a resident A^T needs ldat >= m; it changes the FP32 form's workspace (A^T W as side W of A^T)
+    M.At, M.ldat = 16, 9
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb)) == L.NMF_EINVAL
+    M.ldat = 10
+    nb2 = ctypes.c_size_t(0)
+    assert lib.nmf_anls_workspace_bytes(ctypes.byref(M), 4, ctypes.byref(o), ctypes.byref(nb2)) == L.NMF_OK
+    assert nb2.value > 0
 
 
 def test_struct_layouts_match_header(L):

@@ -155,6 +155,20 @@ def test_video_rows_trajectory():
     print("support agreement W", support_agreement(W, ref["W"]), "H", support_agreement(Ht, ref["Ht"]))
 
 
+def test_video_rows_resident_transpose():
+    """The plain FP32 form with a resident FP32 A^T: the side-H product runs
+    as side W of A^T (here with a split contraction over the 8000 rows) and
+    follows the same oracle trajectory as the form without it."""
+    seed, m, n, k, iters = C.seed_for(5), 8000, 2400, 30, 5
+    Ad = gen.video(seed, m, n)
+    W0, H0 = C.init_w(seed, m, k), C.init_ht(seed, n, k)
+    ref = oracle.anls(k, W0, H0, iters, dense=Ad.cpu().numpy())
+    M = L.Matrix(dense=Ad)
+    M.add_transposed()
+    W, Ht, st = run_gpu(M, k, W0, H0, iters)
+    check_traj(st, ref, "video 8000x2400 k=30, resident A^T")
+
+
 def test_device_generators_bit_identical():
     seed = C.seed_for(5)
     Ad = gen.video(seed, 3000, 2400).cpu().numpy()

@@ -7,6 +7,8 @@ Tolerances come from the arithmetic of each kernel:
   SpMM   FP64 sums in the oracle's order, then one rounding: bit-identical
   BPP    FP64 solves, FP32 outputs: |dx| <= 4 ulp32(x) + 1e-9 max|x|
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -67,6 +69,33 @@ def test_rhs_dense_f32(m, n, k, pad):
     Rho = oracle.rhs_dense_h(A, W.astype(np.float64))
     bh = 1.01 * (m + 1) * U32 * (np.abs(A64).T @ np.abs(W.astype(np.float64)))
     assert np.all(np.abs(Rh - Rho) <= bh + 1e-30), np.max(np.abs(Rh - Rho) / (bh + 1e-30))
+
+
+@pytest.mark.parametrize("rows,cols,ld", [(777, 1030, 1030), (64, 64, 70), (1, 300, 301), (300, 1, 1), (0, 5, 5)])
+def test_transpose_f32(rows, cols, ld):
+    rng = np.random.default_rng(rows + 3 * cols)
+    Xs = rng.standard_normal((rows, ld)).astype(np.float32)
+    X = cuda(Xs)[:, :cols]
+    Xt = L.nmf_transpose_f32(X).cpu().numpy()
+    assert Xt.shape == (cols, rows) and np.array_equal(Xt, Xs[:, :cols].T)
+
+
+@pytest.mark.parametrize("rows,n,k", [(200, 150_000, 30), (300, 70_001, 50), (2400, 40_000, 30)])
+def test_rhs_dense_f32_split_contraction(rows, n, k):
+    """Side W with few row tiles and a long contraction (A^T W over a
+    resident A^T): the contraction is split into ranges whose FP32 partials
+    are summed in FP64; each range is an FP32 chain of nmf_rhs_dense_chain
+    terms, which bounds the error against the exact product."""
+    rng = np.random.default_rng(rows + n + k)
+    A = rng.uniform(0.0, 1.0, (rows, n)).astype(np.float32)
+    Y = rng.uniform(0.0, 1.0, (n, k)).astype(np.float32)
+    terms = ctypes.c_int64(0)
+    assert L.lib().nmf_rhs_dense_chain(L.NMF_SIDE_W, rows, n, k, L.NMF_F32, ctypes.byref(terms)) == L.NMF_OK
+    assert terms.value < n  # the split is taken
+    R = L.nmf_rhs_dense(L.NMF_SIDE_W, cuda(A), cuda(Y)).cpu().numpy().astype(np.float64)
+    Ro = oracle.rhs_dense_w(A, Y.astype(np.float64))
+    b = 1.01 * (terms.value + 1) * U32 * (np.abs(A.astype(np.float64)) @ np.abs(Y.astype(np.float64)))
+    assert np.all(np.abs(R - Ro) <= b + 1e-30), np.max(np.abs(R - Ro) / (b + 1e-30))
 
 
 def test_rhs_dense_empty_contraction():
