@@ -702,7 +702,7 @@ struct PairShared {
   static constexpr int L = pair_lanes(KK);
   static constexpr int P = 64 / L;
   static constexpr int NW = pair_waves(KK);
-  struct Grp {
+  struct alignas(16) Grp {
     double colv[L];
     double rfv[L + 1];
     double dgv[L + 1];
@@ -722,6 +722,12 @@ struct PairShared {
   static constexpr int KS = KK + 1;
   double Gs[KK * KS];
   double Gi[KK * KS];
+  // G_U^{-1} again, transposed (row p holds column p) with an even pitch, so
+  // that z = G_U^{-1} f reads two entries of a lane's row per 16-byte load;
+  // kept where the LDS allows (the 64-lane class reads Gi instead)
+  static constexpr bool kT = KK <= 56;
+  static constexpr int KT = KK + 2;
+  alignas(16) double GiT[kT ? KK * KT : 2];
   Grp grps[NW][P];
   double dsum[NW];
 
@@ -858,7 +864,10 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int idx = t + e * NT;
-      if (idx < KK * KK) Gi[(idx / KK) * KS + idx % KK] = nv[e];
+      if (idx < KK * KK) {
+        Gi[(idx / KK) * KS + idx % KK] = nv[e];
+        if constexpr (PairShared<KK>::kT) sh.GiT[(idx % KK) * PairShared<KK>::KT + idx / KK] = nv[e];
+      }
     }
     __syncthreads();
   }
@@ -927,10 +936,26 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     wave_lds_sync();
     if (inv_ok) {
       double z0 = 0.0, z1 = 0.0;
-      for (int q = 0; q < k; ++q) {
-        const double fq = fw[q];
-        z0 += Gi[q * KS + i0] * fq;
-        z1 += Gi[q * KS + c1] * fq;
+      if constexpr (PairShared<KK>::kT) {
+        // two contraction indices per step, in the same order (entries past
+        // k are zero in both operands)
+        constexpr int KT = PairShared<KK>::KT;
+        const double2* g0 = reinterpret_cast<const double2*>(&sh.GiT[i0 * KT]);
+        const double2* g1 = reinterpret_cast<const double2*>(&sh.GiT[c1 * KT]);
+        const double2* f2 = reinterpret_cast<const double2*>(fw);
+        for (int q2 = 0; q2 < (k + 1) / 2; ++q2) {
+          const double2 fq = f2[q2], a = g0[q2], c = g1[q2];
+          z0 += a.x * fq.x;
+          z0 += a.y * fq.y;
+          z1 += c.x * fq.x;
+          z1 += c.y * fq.y;
+        }
+      } else {
+        for (int q = 0; q < k; ++q) {
+          const double fq = fw[q];
+          z0 += Gi[q * KS + i0] * fq;
+          z1 += Gi[q * KS + c1] * fq;
+        }
       }
       zw[i0] = z0;
       zw[i1] = z1;
