@@ -906,9 +906,10 @@ def cpu_baseline_sparse(seconds, host, m, n, k, seed):
 # ------------------------------------------------------------- other modes --
 def pmc_mode(a):
     """Launches a plain copy of known size, then each product kernel a few
-    times (BF16x3 and FP32 on the video-like matrix, both Gram passes, and
-    with --sparse the CSR products of the sparse workload), for rocprofv3
-    counter collection (FETCH_SIZE / WRITE_SIZE, MFMA busy cycles)."""
+    times (BF16x3 and FP32 on the video-like matrix, the FP32 A^T W also as
+    the side-W product of the resident A^T, both Gram passes, and with
+    --sparse the CSR products of the sparse workload), for rocprofv3 counter
+    collection (FETCH_SIZE / WRITE_SIZE, MFMA busy cycles)."""
     import torch
     b = Bench(a)
     L = b.L
@@ -923,6 +924,8 @@ def pmc_mode(a):
     for _ in range(3):
         L.nmf_rhs_dense(L.NMF_SIDE_W, b.A, b.Ht0)
         L.nmf_rhs_dense(L.NMF_SIDE_H, b.A, b.W0)
+    for _ in range(3):  # A^T W as the plain form forms it: side W of the resident A^T
+        L.nmf_rhs_dense(L.NMF_SIDE_W, b.M.At, b.W0)
     for _ in range(3):
         L.nmf_gram(b.W0)
         L.nmf_gram(b.Ht0)
