@@ -1285,7 +1285,7 @@ int64_t grid_blocks(int K, int64_t batch) {
   return blocks < kMaxBppBlocks ? blocks : kMaxBppBlocks;
 }
 
-// K in {32, 56, 64}: the pivot-row kernel's blocks, then the scan's (a chunk
+// the pivot-row kernel's blocks, then the scan's (a chunk
 // of 64 problems per wavefront)
 int64_t pair_blocks(int K, int64_t batch) {
   const int64_t per_block = (int64_t)(64 / pair_lanes(K)) * pair_waves(K);
@@ -1298,7 +1298,7 @@ int64_t scan_blocks(int64_t batch) {
   return b < kMaxBppBlocks ? b : kMaxBppBlocks;
 }
 int64_t launch_blocks(int K, int64_t batch) {
-  return K >= 32 ? pair_blocks(K, batch) + scan_blocks(batch) : grid_blocks(K, batch);
+  return pair_blocks(K, batch) + scan_blocks(batch);
 }
 
 template <int K>
@@ -1307,7 +1307,7 @@ int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, f
            int warm_cap, uint64_t* counters, double* dot_partial, uint64_t* status_counts, hipStream_t s) {
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
   unsigned long long* sc = reinterpret_cast<unsigned long long*>(status_counts);
-  if constexpr (K >= 32) {
+  if constexpr (K >= 8) {
     const int64_t pb = pair_blocks(K, batch), db = scan_blocks(batch);
     hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(pair_waves(K) * 64), 0, s, k, batch, G, R, ldr, X,
                        ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
@@ -1368,8 +1368,8 @@ int bpp_grouped_launch(int K, const BppItem* items, int64_t n, int grid, int max
   if (n == 0) return NMF_OK;
   unsigned long long* c = reinterpret_cast<unsigned long long*>(counters);
   switch (K) {
-    case 8: hipLaunchKernelGGL(k_bpp_grouped<8>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
-    case 16: hipLaunchKernelGGL(k_bpp_grouped<16>, dim3((unsigned)grid), dim3(256), 0, s, items, n, max_rounds, warm_cap, c); break;
+    case 8: return pair_grouped_launch<8>(items, n, grid, max_rounds, warm_cap, c, s);
+    case 16: return pair_grouped_launch<16>(items, n, grid, max_rounds, warm_cap, c, s);
     case 32: return pair_grouped_launch<32>(items, n, grid, max_rounds, warm_cap, c, s);
     case 56: return pair_grouped_launch<56>(items, n, grid, max_rounds, warm_cap, c, s);
     case 64: return pair_grouped_launch<64>(items, n, grid, max_rounds, warm_cap, c, s);
@@ -1383,8 +1383,8 @@ int bpp_class(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k <= 56
 int bpp_grouped_occupancy(int K, int* per_cu) {
   hipError_t e = hipErrorInvalidValue;
   switch (K) {
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<8>, 256, 0); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_grouped<16>, 256, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<8>, pair_waves(8) * 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<16>, pair_waves(16) * 64, 0); break;
     case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<32>, pair_waves(32) * 64, 0); break;
     case 56: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<56>, pair_waves(56) * 64, 0); break;
     case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_bpp_pair_grouped<64>, pair_waves(64) * 64, 0); break;
