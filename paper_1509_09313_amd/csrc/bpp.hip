@@ -6,25 +6,24 @@
 // exchanges, then the single largest infeasible index), as the paper
 // prescribes by citation.
 //
-// Mapping to the wavefront.  One problem per K lanes (K in {8,16,32}: 64/K
-// problems per wavefront; K in {56,64}: one, lanes >= K idle); lane p owns
-// index p: the row p of G, f_p, x_p.  G is padded to K x K with the identity,
-// so indices k <= p < K never pivot and their updates are no-ops, which keeps
-// every loop fully unrolled over the compile-time K (the row lives in
-// registers).
-// G (k x k FP64) sits in LDS, shared by the block.  Each round solves the
-// passive subsystem G_FF x_F = f_F in FP64 by symmetric elimination in index
-// order (LDL^T with the back-substitution folded into the sweep, i.e.
-// Gauss-Jordan): at pivot j every lane writes its current G-row entry
-// a_pj and its right-hand side to LDS, reads the pivot row from the column
-// (the trailing matrix stays symmetric) and updates its own row.  Active
-// lanes ride along as non-pivot rows, so after the sweep
-//     x_p = rhs_p / pivot_p   (p in F)      y_p = -rhs_p   (p not in F)
-// gives the primal solution and the dual y = G x - f without another pass.
-// The infeasible set V = {p in F: x_p < 0} U {p not in F: y_p < 0} is a
-// ballot; the exchange rule is evaluated identically by every lane.  In the
-// one-problem classes the pivot columns are first packed at the end of the
-// row (see the elimination), so a step touches only later pivots.
+// The passive subsystem G_FF x_F = f_F is solved in FP64 by symmetric
+// elimination in index order (LDL^T with the back-substitution folded into
+// the sweep, i.e. Gauss-Jordan): at pivot j each row subtracts its multiple of
+// the pivot row (the trailing matrix stays symmetric, so the pivot row is read
+// from the column), and after the sweep x_p = rhs_p / pivot_p.  The
+// infeasible set V = {p in F: x_p < 0} U {p not in F: y_p < 0}, y = G x - f,
+// is a ballot; the exchange rule is evaluated identically by every lane of a
+// problem.
+//
+// Two kernels.  k_bpp_pair (below, every k) holds only the pivot rows, a
+// problem per 4 to 32 lanes, and forms the other entries from one product
+// with the solved pivots.  bpp_block, the one-row-per-lane form (one problem
+// per wavefront, K in {56, 64}, lane p owns row p of G, f_p and x_p, G
+// identity-padded to K x K so every loop unrolls over the compile-time K),
+// finishes the problems k_bpp_pair defers: its non-pivot rows ride along
+// through the elimination and come out as y_p = -rhs_p, and its pivot
+// columns are packed at the end of the row (see the elimination), so a step
+// touches only later pivots.
 //
 // Two forms of the same passive-set solve.  Each block also sweeps G once
 // (symmetric sweep operator over the unpinned indices U, FP64, index order)
@@ -60,34 +59,36 @@ struct BppExtras {
   unsigned long long capped = 0, fallback = 0;
 };
 
-// Solves problems b0 + g * P + sub (g = g_first, g_first + g_step, ... while
-// b0 + g * P < b1) of one Gram matrix G; P = 64 / K problems per wavefront,
-// sub selects the lane group.  Loads G into LDS first (after a barrier, so a
-// persistent loop may call it again with another G).  Round and solve
-// statistics are added to cacc (per lane; summed by the caller).
-// Mark of a problem that the two-problem kernel left to the one-problem
+// Mark of a problem that the pivot-row kernel left to the one-row-per-lane
 // kernel: a signalling NaN with a fixed payload in x_0 (arithmetic never
 // produces a signalling NaN, so no solution can carry it).
 constexpr uint32_t kDeferMark = 0xFFBADA55u;
 
-template <int K, bool kRegGi = false, bool kScan = false>
+// The one-row-per-lane kernel (K in {56, 64}, one problem per wavefront):
+// solves the problems of [b0, b1) of one Gram matrix G whose x_0 holds
+// kDeferMark, found 64 at a time (chunk g_first, g_first + g_step, ... of 64
+// problems per wavefront) by a ballot, each from its start set.  Loads G into
+// LDS first (after a barrier, so a persistent loop may call it again with
+// another G).  Round and solve statistics are added to cacc (per lane; summed
+// by the caller).
+template <int K>
 __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, const float* __restrict__ R,
                                           int64_t ldr, float* __restrict__ X, int64_t ldx, const uint64_t* mask_in,
                                           uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
                                           uint8_t* __restrict__ status_out, int max_rounds, int warm_cap, int64_t b0,
                                           int64_t b1, int64_t g_first, int64_t g_step,
                                           unsigned long long (&cacc)[NMF_BPP_COUNTERS], BppExtras& ex) {
-  constexpr int P = 64 / K;
+  static_assert(K >= 56, "one problem per wavefront");
+  constexpr int P = 1;
   __shared__ double Gs[K * K];
   __shared__ double Gi[K * K];
   __shared__ int inv_ok_s;
-  // one slot per lane, plus (one-problem classes) a spare slot 64 for the
-  // packed form's non-pivot lanes
-  constexpr int kSlots = P == 1 ? 65 : 64;
-  __shared__ double colv[kWaves][kSlots];
-  __shared__ double rfv[kWaves][kSlots];
-  __shared__ double dgv[kWaves][P == 1 ? 65 : 1];
-  __shared__ int pix[kWaves][P == 1 ? 65 : 1];
+  // one slot per lane, plus a spare slot 64 for the packed form's non-pivot
+  // lanes
+  __shared__ double colv[kWaves][65];
+  __shared__ double rfv[kWaves][65];
+  __shared__ double dgv[kWaves][65];
+  __shared__ int pix[kWaves][65];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool lane_in = lane < P * K;
@@ -157,38 +158,14 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
   const bool inv_ok = inv_ok_s != 0;
 
   unsigned long long c_rounds = 0, c_solves = 0, c_f1 = 0, c_f2 = 0, c_f3 = 0, c_steps = 0;
-  // kRegGi (the single-matrix kernel's 32-lane class) keeps this lane's
-  // column of G_U^{-1} in registers for every problem's z (W side at
-  // 10^6 x 2400, k = 30: 0.920 -> 0.896 ms); elsewhere it would cost a
-  // wavefront per SIMD
-  double gic[kRegGi ? K : 1];
-  if constexpr (kRegGi) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) gic[q] = Gi[q * K + p];
-  }
 
-  // the next problem's right-hand side and start set are loaded while the
-  // current one is solved
-  const int64_t gstride = g_step;
-  int64_t g = g_first;
-  float f_next = 0.0f;
-  uint64_t m_next = 0;
-  if constexpr (!kScan) {
-    const int64_t b = b0 + g * P + sub;
-    if (lane_in && b < b1 && p < k) f_next = R[b * ldr + p];
-    if (lane_in && b < b1 && mask_in) m_next = mask_in[b];
-  }
-  // Scan form (one problem per wavefront): the problems are those of
-  // [b0, b1) whose x_0 holds kDeferMark, found 64 at a time (a chunk per
-  // wavefront, chunk g_first, g_first + g_step, ...) by a ballot.
-  static_assert(!kScan || P == 1, "the scan form needs one problem per wavefront");
+  // the marked problems: sbits holds the unvisited marks of chunk sc0
   int64_t sc0 = b0 + g_first * 64;
-  uint64_t sbits = 0;
   auto marks = [&](int64_t c0) {
     const int64_t bb = c0 + lane;
     return __ballot(bb < b1 && __float_as_uint(X[bb * ldx]) == kDeferMark);
   };
-  // the next marked problem: sbits holds the unvisited marks of chunk sc0
+  uint64_t sbits = sc0 < b1 ? marks(sc0) : 0ull;
   auto next_mark = [&]() {
     while (sbits == 0ull) {
       sc0 += g_step * 64;
@@ -196,31 +173,14 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
       sbits = marks(sc0);
     }
   };
-  if constexpr (kScan) {
-    sbits = sc0 < b1 ? marks(sc0) : 0ull;
+  next_mark();
+  while (sbits != 0ull) {
+    const int64_t b = sc0 + (__ffsll((unsigned long long)sbits) - 1);
+    sbits &= sbits - 1ull;
     next_mark();
-  }
-  for (; kScan ? sbits != 0ull : b0 + g * P < b1; g += gstride) {
-    int64_t b;
-    bool vprob;
-    double f;
-    uint64_t F;
-    if constexpr (kScan) {
-      b = sc0 + (__ffsll((unsigned long long)sbits) - 1);
-      sbits &= sbits - 1ull;
-      next_mark();
-      vprob = lane_in;
-      f = (vprob && p < k) ? (double)R[b * ldr + p] : 0.0;
-      F = (vprob && mask_in) ? (mask_in[b] & all & ~pinned0) : 0ull;
-    } else {
-      b = b0 + g * P + sub;
-      vprob = lane_in && b < b1;
-      f = (double)f_next;
-      F = vprob ? (m_next & all & ~pinned0) : 0ull;
-      const int64_t bn = b0 + (g + gstride) * P + sub;
-      f_next = (lane_in && bn < b1 && p < k) ? R[bn * ldr + p] : 0.0f;
-      m_next = (lane_in && bn < b1 && mask_in) ? mask_in[bn] : 0ull;
-    }
+    const bool vprob = lane_in;
+    const double f = (vprob && p < k) ? (double)R[b * ldr + p] : 0.0;
+    uint64_t F = (vprob && mask_in) ? (mask_in[b] & all & ~pinned0) : 0ull;
     const bool valid = vprob && p < k;
     uint64_t pinned = pinned0;
     bool warm = F != 0;
@@ -235,15 +195,7 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
       rfv[wave][lane] = f;
       wave_lds_sync();
 #pragma unroll
-      for (int q = 0; q < K; ++q) {
-        double gq;
-        if constexpr (kRegGi) {
-          gq = gic[q];
-        } else {
-          gq = Gi[q * K + p];
-        }
-        z += gq * rfv[wave][base + q];
-      }
+      for (int q = 0; q < K; ++q) z += Gi[q * K + p] * rfv[wave][base + q];
       wave_lds_sync();
     }
 
@@ -389,7 +341,7 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
           x = inF ? own : 0.0;
           y = inF ? 0.0 : corr - f;
         }
-      } else if constexpr (P == 1) {
+      } else {
         // One problem per wavefront, so the pivot set is uniform.  The n_p
         // pivots are packed, in index order, at the end of a K-wide register
         // row (pivot c at position K - n_p + c): each step then updates only
@@ -454,63 +406,6 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
             if (use && p == j) mypiv = piv;
 #pragma unroll
             for (int q = c + 1; q < K; ++q) r[q] -= mlt * colw[q];
-            rf -= mlt * zj;
-            wave_lds_sync();
-          }
-        }
-        const bool inF = (Fe >> p) & 1ull;
-        const bool isPinned = (pinned >> p) & 1ull;
-        if (useInv) {
-          x = inF ? rf : 0.0;
-          y = (inF || isPinned) ? 0.0 : -rf / mypiv;
-        } else {
-          x = inF ? rf / mypiv : 0.0;
-          y = inF ? 0.0 : -rf;
-        }
-      } else {
-        double r[K];
-#pragma unroll
-        for (int q = 0; q < K; ++q) r[q] = Mrow[q * K + p];
-        double rf = rf0, mypiv = 1.0;
-        // The lanes of a problem hold the same pivot set, so the union over
-        // the wavefront's problems is the OR of lanes 0, K, 2K, ... (read into
-        // SGPRs), and the per-index skip test is a scalar branch.
-        uint64_t PU = 0;
-#pragma unroll
-        for (int sp = 0; sp < P; ++sp)
-          PU |= ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(Pv >> 32), sp * K) << 32) |
-                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)Pv, sp * K);
-        {
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            const bool pj = (Pv >> j) & 1ull;
-            if (!((PU >> j) & 1ull)) continue;
-            colv[wave][lane] = r[j];
-            rfv[wave][lane] = rf;
-            wave_lds_sync();
-            const double piv = colv[wave][base + j];
-            const double zj = rfv[wave][base + j];
-            bool use = pj;
-            if (pj && !(piv > 1e-12 * Mrow[j * K + j])) {
-              use = false;
-              if (useInv) {
-                retry = true;
-              } else {
-                F &= ~bit64(j);
-                Fe &= ~bit64(j);
-                pinned |= bit64(j);
-                st |= NMF_BPP_SINGULAR;
-              }
-            }
-            // 1 / piv: hardware estimate and two Newton steps y <- y (2 - piv y)
-            double inv = __builtin_amdgcn_rcp(piv);
-            inv = fma(inv, fma(-piv, inv, 1.0), inv);
-            inv = fma(inv, fma(-piv, inv, 1.0), inv);
-            inv = use ? inv : 0.0;
-            const double mlt = (use && p != j) ? r[j] * inv : 0.0;
-            if (use && p == j) mypiv = piv;
-#pragma unroll
-            for (int q = j + 1; q < K; ++q) r[q] -= mlt * colv[wave][base + q];
             rf -= mlt * zj;
             wave_lds_sync();
           }
@@ -665,30 +560,32 @@ __device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __rest
   }
 }
 
-// ---- Two problems per wavefront for 32 < k <= 64 ----------------------------
+// ---- The pivot-row kernel (every k) ------------------------------------------
 // Whenever G_U^{-1} is available, a round eliminates over the smaller of F
 // and its complement in U, so it has at most floor(k / 2) pivots: at most
-// KK / 2 (28 or 32) for the class KK in {56, 64}.  The elimination needs only
-// the pivot rows, so a half-wavefront of 32 lanes holds them (pivot c of n_p,
-// in index order, at position KK / 2 - n_p + c) and one wavefront carries
-// two problems, lanes 0-31 and 32-63.  Lane h of a half owns indices h and
-// h + 32 (f, z, x, the dual y and the KKT test).  The non-pivot entries come
-// after the elimination from one product with the solved pivots:
+// KK / 2 for the class KK in {8, 16, 32, 56, 64}.  The elimination needs only
+// the pivot rows, so L lanes per problem (KK / 2, or 32 for KK >= 56) hold
+// them, pivot c of n_p (in index order) at position KK / 2 - n_p + c, and a
+// wavefront carries 64 / L problems (16, 8, 4, 2, 2).  Lane h of a problem
+// owns indices h and h + L (f, z, x, the dual y and the KKT test).  The
+// non-pivot entries come after the elimination from one product with the
+// solved pivots:
 //     direct form  (pivots F):  y_i = sum_c G_{i,j_c} x_c - f_i
 //     inverse form (pivots A):  x_i = z_i - sum_c (G_U^{-1})_{i,j_c} v_c,
-// instead of riding along in the elimination as the one-problem kernel's
+// instead of riding along in the elimination as the one-row-per-lane form's
 // non-pivot rows do.  The pivot rows' arithmetic, and its order, is that of
-// the one-problem kernel; only the non-pivot entries round differently.
+// the one-row-per-lane form; only the non-pivot entries round differently.
 // A round with more than KK / 2 pivots (G_U^{-1} unavailable, or a failed
 // pivot of the inverse form forcing the direct form with a large F) cannot
 // be held: the problem is left untouched except for kDeferMark in x_0, and
-// the one-problem kernel's scan form solves it from its start afterwards.
-// Blocks of 12 wavefronts (one block per CU, 3 wavefronts per SIMD, the most
-// that 168 VGPRs allow) share G and G_U^{-1} in LDS; G_U^{-1} comes from the
-// symmetric sweep run by the whole block.
+// the one-row-per-lane form solves it from its start afterwards.
+// Blocks of 12 wavefronts (KK >= 56: one block per CU at 3 per SIMD, the most
+// that their 151-155 VGPRs allow) or 8 (KK <= 32: two blocks per CU at 4 per
+// SIMD) share G and G_U^{-1} in LDS; G_U^{-1} comes from the symmetric sweep
+// run by the whole block.
 constexpr int kPairBlocks = 256;
 // wavefronts per block of the class KK (one block per CU for KK >= 56; two
-// for KK = 32, whose blocks are smaller in LDS)
+// for KK <= 32, whose blocks are smaller in LDS)
 constexpr int pair_waves(int KK) { return KK >= 56 ? 12 : 8; }
 // lanes per problem: indices h and h + L belong to lane h of a group
 constexpr int pair_lanes(int KK) { return KK >= 56 ? 32 : KK / 2; }
@@ -816,7 +713,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
   // G_U^{-1} by the symmetric sweep over the unpinned indices in index order,
   // on a row-major working copy W (row i in W[i][.]): sweeping j maps
   // W_jj -> -1/d, W_jl -> W_jl / d, W_ij -> W_ij / d and
-  // W_il -> W_il - (W_ij / d) W_lj (d = W_jj), as the one-problem kernel does
+  // W_il -> W_il - (W_ij / d) W_lj (d = W_jj), as the one-row-per-lane form does
   // with one row per lane; then (G_U^{-1})_{q,p} = -W[p][q] on U x U.
   bool inv_ok = true;
   for (int j = 0; j < k; ++j) {
@@ -967,7 +864,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       const bool useInv = inv_ok && !forceG && __popcll(Ae) < __popcll(Fe);
       uint64_t Pv = useInv ? Ae : Fe;
       if (__popcll(Pv) > NP) {
-        // more pivots than lanes: left to the one-problem kernel
+        // more pivots than lanes: left to the one-row-per-lane form
         defer = true;
         done = true;
         Fe = 0;
@@ -1188,7 +1085,7 @@ k_bpp_pair_grouped(const nmf::BppItem* __restrict__ items, int64_t n, int max_ro
   sh.flush(counters, nullptr, nullptr);
 }
 
-// The one-problem kernel's scan form: solves the problems that k_bpp_pair
+// The one-row-per-lane form: solves the problems that k_bpp_pair
 // marked, from their start sets; dot_partial has one entry per block.
 template <int K>
 __global__ __launch_bounds__(256) void k_bpp_deferred(int k, int64_t batch, const double* __restrict__ G,
@@ -1212,32 +1109,15 @@ __global__ __launch_bounds__(256) void k_bpp_deferred(int k, int64_t batch, cons
   }
   unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
   BppExtras ex;
-  bpp_block<K, false, true>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0,
+  bpp_block<K>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0,
                             batch, w0, ws, cacc, ex);
   if (counters) flush_counters(cacc, counters);
   if (dot_partial || status_counts) flush_extras(ex, dot_partial, status_counts);
 }
 
-template <int K>
-__global__ __launch_bounds__(256) void k_bpp(int k, int64_t batch, const double* __restrict__ G,
-                                             const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
-                                             int64_t ldx, const uint64_t* mask_in,
-                                             uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
-                                             uint8_t* __restrict__ status_out, int max_rounds, int warm_cap,
-                                             unsigned long long* __restrict__ counters,
-                                             double* __restrict__ dot_partial,
-                                             unsigned long long* __restrict__ status_counts) {
-  unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
-  BppExtras ex;
-  const int wave = threadIdx.x >> 6;
-  bpp_block<K, K == 32>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0,
-                        batch, (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves, cacc, ex);
-  if (counters) flush_counters(cacc, counters);
-  if (dot_partial || status_counts) flush_extras(ex, dot_partial, status_counts);
-}
-
-// Grouped scan form: for each item with marked problems, the one-problem
-// kernel solves them (items without marks are skipped before G is loaded).
+// Grouped form of the same: for each item with marked problems, the
+// one-row-per-lane form solves them (items without marks are skipped before G
+// is loaded).
 template <int K>
 __global__ __launch_bounds__(256) void k_bpp_deferred_grouped(const nmf::BppItem* __restrict__ items, int64_t n,
                                                               int max_rounds, int warm_cap,
@@ -1253,37 +1133,13 @@ __global__ __launch_bounds__(256) void k_bpp_deferred_grouped(const nmf::BppItem
       any |= bb < it.b1 && __float_as_uint(it.X[bb * it.ldx]) == kDeferMark;
     }
     if (!__syncthreads_or(any)) continue;
-    bpp_block<K, false, true>(it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status,
+    bpp_block<K>(it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status,
                               max_rounds, warm_cap, it.b0, it.b1, wave, kWaves, cacc, ex);
   }
   if (counters) flush_counters(cacc, counters);
 }
 
-// Grouped form: a persistent walk over items, each a range of problems of
-// one Gram matrix (start sets from, and final sets to, the item's masks when
-// it has them; cold starts otherwise).
-template <int K>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 56 ? 2 : 1))) void k_bpp_grouped(const nmf::BppItem* __restrict__ items, int64_t n,
-                                                     int max_rounds, int warm_cap,
-                                                     unsigned long long* __restrict__ counters) {
-  unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
-  BppExtras ex;  // not used here
-  const int wave = threadIdx.x >> 6;
-  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-    const nmf::BppItem it = items[i];
-    bpp_block<K>(it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status, max_rounds, warm_cap,
-                 it.b0, it.b1, wave, kWaves, cacc, ex);
-  }
-  if (counters) flush_counters(cacc, counters);
-}
-
 constexpr int64_t kMaxBppBlocks = 1024;
-
-int64_t grid_blocks(int K, int64_t batch) {
-  const int64_t waves = nmf::cdiv(batch, 64 / K);
-  const int64_t blocks = nmf::cdiv(waves, kWaves);
-  return blocks < kMaxBppBlocks ? blocks : kMaxBppBlocks;
-}
 
 // the pivot-row kernel's blocks, then the scan's (a chunk
 // of 64 problems per wavefront)
@@ -1307,23 +1163,16 @@ int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, f
            int warm_cap, uint64_t* counters, double* dot_partial, uint64_t* status_counts, hipStream_t s) {
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
   unsigned long long* sc = reinterpret_cast<unsigned long long*>(status_counts);
-  if constexpr (K >= 8) {
-    const int64_t pb = pair_blocks(K, batch), db = scan_blocks(batch);
-    hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(pair_waves(K) * 64), 0, s, k, batch, G, R, ldr, X,
-                       ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
-    NMF_TRY(nmf::launch_status("nnls_bpp_batched (pivot rows only)"));
-    // deferred problems: one per wavefront, in the class that holds every k <= K
-    constexpr int KD = K == 64 ? 64 : 56;
-    hipLaunchKernelGGL(k_bpp_deferred<KD>, dim3((unsigned)db), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
-                       mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial ? dot_partial + pb : nullptr,
-                       sc);
-    return nmf::launch_status("nnls_bpp_batched (deferred problems)");
-  } else {
-    const int64_t blocks = grid_blocks(K, batch);
-    hipLaunchKernelGGL(k_bpp<K>, dim3((unsigned)blocks), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
-                       mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
-    return nmf::launch_status("nnls_bpp_batched");
-  }
+  const int64_t pb = pair_blocks(K, batch), db = scan_blocks(batch);
+  hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(pair_waves(K) * 64), 0, s, k, batch, G, R, ldr, X,
+                     ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
+  NMF_TRY(nmf::launch_status("nnls_bpp_batched (pivot rows only)"));
+  // deferred problems: one per wavefront, in the class that holds every k <= K
+  constexpr int KD = K == 64 ? 64 : 56;
+  hipLaunchKernelGGL(k_bpp_deferred<KD>, dim3((unsigned)db), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
+                     mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial ? dot_partial + pb : nullptr,
+                     sc);
+  return nmf::launch_status("nnls_bpp_batched (deferred problems)");
 }
 
 }  // namespace
