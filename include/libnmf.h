@@ -167,7 +167,8 @@ int nmf_rhs_csr(int64_t rows, int64_t cols, int k, const int64_t* rowptr, const 
  * For each row b < batch: X[b] = argmin_{x >= 0} 1/2 x^T G x - R[b]^T x,
  * i.e. min ||C x - c||^2 with C^T C = G, C^T c = R[b] (Eq. single NLS, KKT
  * conditions Eq. KKT).  G: k x k FP64, symmetric (device).  R: FP32 rows,
- * ldr >= k; X: FP32 rows, ldx >= k (X may alias R only if ldx == ldr).
+ * ldr >= k; X: FP32 rows, ldx >= k (X may alias R only if ldx == ldr; then
+ * every problem is solved by the slower one-row-per-lane form).
  * mask_in (optional): initial passive sets (bit i = index i passive); NULL
  * or an all-zero mask is a cold start.  mask_out (optional): final passive
  * sets (may alias mask_in).  rounds (optional): KKT checks per problem

@@ -66,8 +66,9 @@ constexpr uint32_t kDeferMark = 0xFFBADA55u;
 
 // The one-row-per-lane kernel (K in {56, 64}, one problem per wavefront):
 // solves the problems of [b0, b1) of one Gram matrix G whose x_0 holds
-// kDeferMark, found 64 at a time (chunk g_first, g_first + g_step, ... of 64
-// problems per wavefront) by a ballot, each from its start set.  Loads G into
+// kDeferMark (every problem of the range with `every`), found 64 at a time
+// (chunk g_first, g_first + g_step, ... of 64 problems per wavefront) by a
+// ballot, each from its start set.  Loads G into
 // LDS first (after a barrier, so a persistent loop may call it again with
 // another G).  Round and solve statistics are added to cacc (per lane; summed
 // by the caller).
@@ -77,7 +78,8 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
                                           uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
                                           uint8_t* __restrict__ status_out, int max_rounds, int warm_cap, int64_t b0,
                                           int64_t b1, int64_t g_first, int64_t g_step,
-                                          unsigned long long (&cacc)[NMF_BPP_COUNTERS], BppExtras& ex) {
+                                          unsigned long long (&cacc)[NMF_BPP_COUNTERS], BppExtras& ex,
+                                          bool every = false) {
   static_assert(K >= 56, "one problem per wavefront");
   constexpr int P = 1;
   __shared__ double Gs[K * K];
@@ -163,7 +165,7 @@ __device__ __forceinline__ void bpp_block(int k, const double* __restrict__ G, c
   int64_t sc0 = b0 + g_first * 64;
   auto marks = [&](int64_t c0) {
     const int64_t bb = c0 + lane;
-    return __ballot(bb < b1 && __float_as_uint(X[bb * ldx]) == kDeferMark);
+    return __ballot(bb < b1 && (every || __float_as_uint(X[bb * ldx]) == kDeferMark));
   };
   uint64_t sbits = sc0 < b1 ? marks(sc0) : 0ull;
   auto next_mark = [&]() {
@@ -1085,34 +1087,40 @@ k_bpp_pair_grouped(const nmf::BppItem* __restrict__ items, int64_t n, int max_ro
   sh.flush(counters, nullptr, nullptr);
 }
 
-// The one-row-per-lane form: solves the problems that k_bpp_pair
-// marked, from their start sets; dot_partial has one entry per block.
+// The one-row-per-lane form: solves the problems that k_bpp_pair marked, from
+// their start sets, or with `every` all of them (when X overlaps R, so that
+// no mark may be written).  dot_partial: one entry per block at
+// dot_partial[dot_skip + block]; with `every` block 0 also zeros the
+// dot_skip entries before them (the pivot-row kernel's, which did not run).
 template <int K>
 __global__ __launch_bounds__(256) void k_bpp_deferred(int k, int64_t batch, const double* __restrict__ G,
-                                                      const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
+                                                      const float* __restrict__ R, int64_t ldr, float* X,
                                                       int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
                                                       uint8_t* __restrict__ rounds_out,
                                                       uint8_t* __restrict__ status_out, int max_rounds, int warm_cap,
                                                       unsigned long long* __restrict__ counters,
-                                                      double* __restrict__ dot_partial,
-                                                      unsigned long long* __restrict__ status_counts) {
+                                                      double* __restrict__ dot_partial, int64_t dot_skip,
+                                                      unsigned long long* __restrict__ status_counts, int every) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t w0 = (int64_t)blockIdx.x * kWaves + wave, ws = (int64_t)gridDim.x * kWaves;
+  if (every && blockIdx.x == 0 && dot_partial)
+    for (int64_t e = threadIdx.x; e < dot_skip; e += 256) dot_partial[e] = 0.0;
+  double* dp = dot_partial ? dot_partial + dot_skip : nullptr;
   bool any = false;
   for (int64_t c0 = w0 * 64; c0 < batch; c0 += ws * 64) {
     const int64_t bb = c0 + lane;
-    any |= bb < batch && __float_as_uint(X[bb * ldx]) == kDeferMark;
+    any |= bb < batch && (every || __float_as_uint(X[bb * ldx]) == kDeferMark);
   }
   if (!__syncthreads_or(any)) {
-    if (threadIdx.x == 0 && dot_partial) dot_partial[blockIdx.x] = 0.0;
+    if (threadIdx.x == 0 && dp) dp[blockIdx.x] = 0.0;
     return;
   }
   unsigned long long cacc[NMF_BPP_COUNTERS] = {0, 0, 0, 0, 0, 0};
   BppExtras ex;
-  bpp_block<K>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0,
-                            batch, w0, ws, cacc, ex);
+  bpp_block<K>(k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0, batch, w0,
+               ws, cacc, ex, every != 0);
   if (counters) flush_counters(cacc, counters);
-  if (dot_partial || status_counts) flush_extras(ex, dot_partial, status_counts);
+  if (dp || status_counts) flush_extras(ex, dp, status_counts);
 }
 
 // Grouped form of the same: for each item with marked problems, the
@@ -1164,15 +1172,21 @@ int launch(int k, int64_t batch, const double* G, const float* R, int64_t ldr, f
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
   unsigned long long* sc = reinterpret_cast<unsigned long long*>(status_counts);
   const int64_t pb = pair_blocks(K, batch), db = scan_blocks(batch);
-  hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(pair_waves(K) * 64), 0, s, k, batch, G, R, ldr, X,
-                     ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
-  NMF_TRY(nmf::launch_status("nnls_bpp_batched (pivot rows only)"));
-  // deferred problems: one per wavefront, in the class that holds every k <= K
+  // X overlapping R (allowed with ldx == ldr) leaves no room for a deferral
+  // mark: then the one-row-per-lane form solves every problem instead
+  const uintptr_t xb = (uintptr_t)X, xe = (uintptr_t)(X + (batch - 1) * ldx + k);
+  const uintptr_t rb = (uintptr_t)R, re = (uintptr_t)(R + (batch - 1) * ldr + k);
+  const int every = xb < re && rb < xe;
+  if (!every) {
+    hipLaunchKernelGGL(k_bpp_pair<K>, dim3((unsigned)pb), dim3(pair_waves(K) * 64), 0, s, k, batch, G, R, ldr, X,
+                       ldx, mask_in, mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, sc);
+    NMF_TRY(nmf::launch_status("nnls_bpp_batched (pivot rows only)"));
+  }
+  // deferred problems (or all): one per wavefront, in the class that holds every k <= K
   constexpr int KD = K == 64 ? 64 : 56;
   hipLaunchKernelGGL(k_bpp_deferred<KD>, dim3((unsigned)db), dim3(256), 0, s, k, batch, G, R, ldr, X, ldx, mask_in,
-                     mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial ? dot_partial + pb : nullptr,
-                     sc);
-  return nmf::launch_status("nnls_bpp_batched (deferred problems)");
+                     mask_out, rounds, status, max_rounds, warm_cap, cnt, dot_partial, pb, sc, every);
+  return nmf::launch_status("nnls_bpp_batched (one row per lane)");
 }
 
 }  // namespace

@@ -246,6 +246,34 @@ def test_bpp_deferred_problems():
     assert np.mean(rounds.astype(np.int32) == ref[2]) >= 0.99
 
 
+def test_bpp_solutions_in_place_of_rhs():
+    """X may alias R (ldx == ldr): then no deferral mark may be written into
+    x_0, and the one-row-per-lane form solves every problem.  Checked where
+    the pivot-row kernel would defer (k = 48, singular G) and where it would
+    not (k = 30), against the oracle."""
+    rng = np.random.default_rng(13)
+    k, batch = 48, 700
+    Cm = rng.uniform(0.0, 1.0, (150, k))
+    Cm[:, 40] = Cm[:, 9]
+    G = Cm.T @ Cm
+    xs = rng.uniform(0.2, 1.0, (batch, k)) * (rng.uniform(size=(batch, k)) < 0.5)
+    R = ((xs @ Cm.T + 0.05 * rng.standard_normal((batch, 150))) @ Cm).astype(np.float32)
+    ref = oracle.bpp_batched(G, R.astype(np.float64))
+    Rd = cuda(R)
+    X, masks, rounds, st = (t.cpu().numpy() for t in L.nnls_bpp_batched(cuda(G), Rd, X=Rd))
+    assert np.all(np.isfinite(X)) and np.array_equal(X, Rd.cpu().numpy())
+    assert np.array_equal(st.astype(np.int32), ref[3])
+    res_gpu = Cm @ X.T.astype(np.float64)
+    res_orc = Cm @ ref[0].T
+    assert np.max(np.abs(res_gpu - res_orc)) <= 1e-5 * np.abs(res_orc).max()
+    rng = np.random.default_rng(14)
+    G, R = nmf_like_problems(rng, 30, 2000)
+    ref = oracle.bpp_batched(G, R.astype(np.float64))
+    Rd = cuda(R)
+    out = L.nnls_bpp_batched(cuda(G), Rd, X=Rd)
+    compare_bpp(G, R, out, ref)
+
+
 @pytest.mark.parametrize("k", [40, 50, 64])
 def test_bpp_counters_two_problem_kernel(k):
     """Round and pivot-step counters of the k > 32 kernels equal the sums of
