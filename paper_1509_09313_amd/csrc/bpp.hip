@@ -581,14 +581,15 @@ __device__ __forceinline__ void flush_extras(const BppExtras& ex, double* __rest
 // pivot of the inverse form forcing the direct form with a large F) cannot
 // be held: the problem is left untouched except for kDeferMark in x_0, and
 // the one-row-per-lane form solves it from its start afterwards.
-// Blocks of 12 wavefronts (KK >= 56: one block per CU at 3 per SIMD, the most
-// that their 151-155 VGPRs allow) or 8 (KK <= 32: two blocks per CU at 4 per
-// SIMD) share G and G_U^{-1} in LDS; G_U^{-1} comes from the symmetric sweep
-// run by the whole block.
+// Blocks of 16 wavefronts (KK = 56: one block per CU, 4 per SIMD within 128
+// VGPRs and 155 KB of LDS), 12 (KK = 64: one per CU at 3 per SIMD, the most
+// that its 135-137 VGPRs allow) or 8 (KK <= 32: two per CU at 4 per SIMD)
+// share G and G_U^{-1} in LDS; G_U^{-1} comes from the symmetric sweep run by
+// the whole block.
 constexpr int kPairBlocks = 256;
 // wavefronts per block of the class KK (one block per CU for KK >= 56; two
 // for KK <= 32, whose blocks are smaller in LDS)
-constexpr int pair_waves(int KK) { return KK >= 56 ? 12 : 8; }
+constexpr int pair_waves(int KK) { return KK == 64 ? 12 : KK == 56 ? 16 : 8; }
 // lanes per problem: indices h and h + L belong to lane h of a group
 constexpr int pair_lanes(int KK) { return KK >= 56 ? 32 : KK / 2; }
 
@@ -605,7 +606,7 @@ struct PairShared {
     double colv[L];
     double rfv[L + 1];
     double dgv[L + 1];
-    double vv[2 * L];
+    double vv[L];
     double fv[2 * L];  // the problem's right-hand side f
     double zv[2 * L];  // z = G_U^{-1} f
     double dotv[L];    // per lane: sum of f_i x_i over its finished problems
@@ -639,7 +640,11 @@ struct PairShared {
   }
   // block sums: the dot partial in a fixed order, the counts by atomics
   __device__ void flush(unsigned long long* counters, double* dot_partial, unsigned long long* status_counts) {
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // (an opaque copy of the thread index: the addresses below are formed
+    // here, not kept alive from the kernel's start)
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int lane = t & 63, wave = t >> 6;
     double dot = grps[wave][lane / L].dotv[lane % L];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o, 64);
@@ -782,9 +787,13 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
   const int64_t npair = (b1 - b0 + P - 1) / P;  // problem groups, one per wavefront
   const int64_t gstride = g_step;
   int64_t g = g_first;
+  // the next problem's right-hand side and start set are loaded during this
+  // one's solve, except in the 56-lane class, whose 16-wavefront blocks leave
+  // no registers for them
+  constexpr bool kPrefetch = KK <= 32;
   float fn0 = 0.0f, fn1 = 0.0f;
   uint64_t mn = 0;
-  {
+  if constexpr (kPrefetch) {
     const int64_t b = b0 + P * g + grp;
     if (g < npair && b < b1) {
       if (i0 < k) fn0 = R[b * ldr + i0];
@@ -798,15 +807,24 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     const bool val0 = vprob && i0 < k, val1 = vprob && i1 < k;
     double* fw = gs.fv;
     double* zw = gs.zv;
-    fw[i0] = (double)fn0;
-    fw[i1] = (double)fn1;
-    uint64_t F = vprob ? (mn & all & ~pinned0) : 0ull;
-    {
+    uint64_t F;
+    if constexpr (kPrefetch) {
+      fw[i0] = (double)fn0;
+      fw[i1] = (double)fn1;
+      F = vprob ? (mn & all & ~pinned0) : 0ull;
       const int64_t bn = b0 + P * (g + gstride) + grp;
       const bool vn = g + gstride < npair && bn < b1;
       fn0 = (vn && i0 < k) ? R[bn * ldr + i0] : 0.0f;
       fn1 = (vn && i1 < k) ? R[bn * ldr + i1] : 0.0f;
       mn = (vn && mask_in) ? mask_in[bn] : 0ull;
+    } else {
+      // (opaque copies of the owned indices, so that the per-lane addresses
+      // are formed here rather than kept through the problem loop)
+      int o0 = i0, o1 = i1;
+      asm volatile("" : "+v"(o0), "+v"(o1));
+      fw[i0] = val0 ? (double)R[b * ldr + o0] : 0.0;
+      fw[i1] = val1 ? (double)R[b * ldr + o1] : 0.0;
+      F = (vprob && mask_in) ? (mask_in[b] & all & ~pinned0) : 0ull;
     }
     uint64_t pinned = pinned0;
     bool warm = F != 0;
@@ -819,14 +837,16 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     // stores a finished problem's x (as FP32) and its share of the dot sum
     auto finish = [&](double x0, double x1) {
       double d = gs.dotv[h];
+      int o0 = i0, o1 = i1;
+      asm volatile("" : "+v"(o0), "+v"(o1));
       if (val0) {
         const float xs = (float)x0;
-        X[b * ldx + i0] = xs;
+        X[b * ldx + o0] = xs;
         d += (double)xs * fw[i0];
       }
       if (val1) {
         const float xs = (float)x1;
-        X[b * ldx + i1] = xs;
+        X[b * ldx + o1] = xs;
         d += (double)xs * fw[i1];
       }
       gs.dotv[h] = d;
@@ -861,15 +881,13 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     }
 
     while (__ballot(!done) != 0) {
-      uint64_t Fe = done ? 0ull : F;
       const uint64_t Ae = done ? 0ull : (all & ~pinned & ~F);
-      const bool useInv = inv_ok && !forceG && __popcll(Ae) < __popcll(Fe);
-      uint64_t Pv = useInv ? Ae : Fe;
+      const bool useInv = inv_ok && !forceG && __popcll(Ae) < __popcll(done ? 0ull : F);
+      uint64_t Pv = useInv ? Ae : (done ? 0ull : F);
       if (__popcll(Pv) > NP) {
         // more pivots than lanes: left to the one-row-per-lane form
         defer = true;
         done = true;
-        Fe = 0;
         Pv = 0;
       }
       const double* Mrow = useInv ? Gi : Gs;
@@ -933,7 +951,6 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
             retry = true;
           } else {
             F &= ~bit64(j);
-            Fe &= ~bit64(j);
             pinned |= bit64(j);
             st |= NMF_BPP_SINGULAR;
           }
@@ -944,7 +961,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
         inv = use ? inv : 0.0;
         const double mlt = (use && !pl) ? r[c] * inv : 0.0;
         if (use && pl) mypiv = piv;
-        // (the pivot row is read eight entries at a time, so that its loads
+        // (the pivot row is read four entries at a time, so that its loads
         // do not all stay in flight beside the row)
 #pragma unroll
         for (int q = c + 1; q < NP; ++q) {
@@ -973,7 +990,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       }
       const double own0 = vw[s0 < L ? s0 : 0], own1 = vw[s1 < L ? s1 : 0];
       wave_lds_sync();
-      const bool inF0 = (Fe >> i0) & 1ull, inF1 = (Fe >> i1) & 1ull;
+      const bool inF0 = !done && ((F >> i0) & 1ull), inF1 = !done && ((F >> i1) & 1ull);
       const bool pin0 = (pinned >> i0) & 1ull, pin1 = (pinned >> i1) & 1ull;
       double x0, y0, x1, y1;
       if (useInv) {
@@ -997,7 +1014,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       if (retry) forceG = true;
       if (live) {
         if (h == 0) {
-          const uint32_t nf = (uint32_t)__popcll(Fe);
+          const uint32_t nf = (uint32_t)__popcll(F);
           pc[4] += (uint32_t)np;
           if (nf) {
             pc[0] += 1;
@@ -1057,7 +1074,7 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
 }
 
 template <int KK>
-__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK >= 56 ? 3 : 4))) void k_bpp_pair(
+__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK == 64 ? 3 : 4))) void k_bpp_pair(
     int k, int64_t batch, const double* __restrict__ G, const float* __restrict__ R, int64_t ldr,
     float* __restrict__ X, int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out, uint8_t* __restrict__ rounds_out,
     uint8_t* __restrict__ status_out, int max_rounds, int warm_cap, unsigned long long* __restrict__ counters,
@@ -1066,14 +1083,14 @@ __global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_pe
   constexpr int NW = pair_waves(KK);
   sh.clear_stats();
   pair_block<KK>(sh, k, G, R, ldr, X, ldx, mask_in, mask_out, rounds_out, status_out, max_rounds, warm_cap, 0, batch,
-                 (int64_t)blockIdx.x * NW + (threadIdx.x >> 6), (int64_t)gridDim.x * NW);
+                 (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), (int64_t)gridDim.x * NW);
   sh.flush(counters, dot_partial, status_counts);
 }
 
 // Grouped form: a persistent walk over items (ranges of problems of one G),
 // each block taking whole items.
 template <int KK>
-__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK >= 56 ? 3 : 4))) void
+__global__ __launch_bounds__(pair_waves(KK) * 64) __attribute__((amdgpu_waves_per_eu(KK == 64 ? 3 : 4))) void
 k_bpp_pair_grouped(const nmf::BppItem* __restrict__ items, int64_t n, int max_rounds, int warm_cap,
                    unsigned long long* __restrict__ counters) {
   __shared__ PairShared<KK> sh;
@@ -1082,7 +1099,7 @@ k_bpp_pair_grouped(const nmf::BppItem* __restrict__ items, int64_t n, int max_ro
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     const nmf::BppItem it = items[i];
     pair_block<KK>(sh, it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status, max_rounds,
-                   warm_cap, it.b0, it.b1, threadIdx.x >> 6, NW);
+                   warm_cap, it.b0, it.b1, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), NW);
   }
   sh.flush(counters, nullptr, nullptr);
 }
