@@ -901,10 +901,10 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       const int s1 = pv1 ? off + __popcll(Pv & (bit64(i1) - 1ull)) : L;
       pw[s0] = i0;
       rfw[s0] = useInv ? zw[i0] : fw[i0];
-      dgw[s0] = Mrow[i0 * KS + i0];
+      dgw[s0] = 1e-12 * Mrow[i0 * KS + i0];
       pw[s1] = i1;
       rfw[s1] = useInv ? zw[i1] : fw[i1];
-      dgw[s1] = Mrow[c1 * KS + c1];
+      dgw[s1] = 1e-12 * Mrow[c1 * KS + c1];
       wave_lds_sync();
       const bool mine = h >= off && h < NP;
       const int jh = mine ? pw[h] : 0;
@@ -942,18 +942,21 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
         wave_lds_sync();
         const double piv = colw[c];
         const double zj = rfw[c];
-        bool use = act;
-        if (act && !(piv > 1e-12 * dgw[c])) {
-          use = false;
-          if (pl) myok = false;
+        // a failed pivot (rare) is handled behind a wave-uniform branch, so
+        // that the common step carries no divergent control flow
+        const bool bad = (!(piv > dgw[c])) & act;
+        const bool use = act & !bad;
+        if (__ballot(bad) != 0ull) {
+          // (selects rather than branches: the compiler would otherwise fold
+          // this test into divergent control flow around every step)
           const int j = pw[c];
-          if (useInv) {
-            retry = true;
-          } else {
-            F &= ~bit64(j);
-            pinned |= bit64(j);
-            st |= NMF_BPP_SINGULAR;
-          }
+          myok = myok & !(bad & pl);
+          retry = retry | (bad & useInv);
+          const bool pin = bad & !useInv;
+          const uint64_t drop = pin ? bit64(j) : 0ull;
+          F &= ~drop;
+          pinned |= drop;
+          st |= pin ? NMF_BPP_SINGULAR : 0;
         }
         double inv = __builtin_amdgcn_rcp(piv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
