@@ -630,6 +630,8 @@ struct PairShared {
   alignas(16) double GiT[kT ? KK * KT : 2];
   Grp grps[NW][P];
   double dsum[NW];
+  // the sweep's pivot column, in two alternating buffers
+  double colbuf[2][KK];
 
   __device__ void clear_stats() {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -707,7 +709,6 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     const int q = idx / KK, pp = idx - q * KK;
     const double v = (q < k && pp < k) ? G[q * k + pp] : (q == pp ? 1.0 : 0.0);
     Gs[q * KS + pp] = v;
-    Gi[q * KS + pp] = v;
   }
   __syncthreads();
   const uint64_t all = (k == 64) ? ~0ull : (bit64(k) - 1ull);
@@ -718,64 +719,74 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     if (Gs[q * KS + q] <= 1e-14 * dmax) pinned0 |= bit64(q);
 
   // G_U^{-1} by the symmetric sweep over the unpinned indices in index order,
-  // on a row-major working copy W (row i in W[i][.]): sweeping j maps
-  // W_jj -> -1/d, W_jl -> W_jl / d, W_ij -> W_ij / d and
-  // W_il -> W_il - (W_ij / d) W_lj (d = W_jj), as the one-row-per-lane form does
-  // with one row per lane; then (G_U^{-1})_{q,p} = -W[p][q] on U x U.
+  // on a row-major working copy W: sweeping j maps W_jj -> -1/d,
+  // W_jl -> W_jl / d, W_ij -> W_ij / d and W_il -> W_il - (W_ij / d) W_lj
+  // (d = W_jj), as the one-row-per-lane form does with one row per lane; then
+  // (G_U^{-1})_{q,p} = -W[p][q] on U x U.  Thread t keeps the entries
+  // (i, l) = (t / KK + e SR, t % KK), e < kPer, in registers through the whole
+  // sweep; a step needs only the old column j (W_ij, W_lj and d), which its
+  // owners publish in one of two LDS buffers (alternating, so one barrier per
+  // step suffices).
+  constexpr int SR = (KK + kPer - 1) / kPer;  // row groups: KK * SR <= NT
+  static_assert(KK * SR <= NT, "every entry of W has an owner");
+  const int wl = t % KK, wr = t / KK;
+  const bool wown = t < KK * SR;
+  double w[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int i = wr + e * SR;
+    w[e] = (wown && i < KK) ? Gs[i * KS + wl] : 0.0;
+  }
   bool inv_ok = true;
+  int par = 0;
   for (int j = 0; j < k; ++j) {
     if ((pinned0 >> j) & 1ull) continue;
-    const double d = Gi[j * KS + j];
+    double* cb = sh.colbuf[par];
+    par ^= 1;
+    if (wown && wl == j) {
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int i = wr + e * SR;
+        if (i < KK) cb[i] = w[e];
+      }
+    }
+    __syncthreads();
+    // (every read of the step is issued here, and the update is branch-free;
+    // entries past KK and threads without entries compute values that are
+    // never stored)
+    const double d = cb[j];
+    const double wlj = cb[wl];
+    double wij[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int i = wr + e * SR;
+      wij[e] = cb[i < KK ? i : 0];
+    }
     if (!(d > 1e-6 * Gs[j * KS + j])) inv_ok = false;
     const double inv = 1.0 / d;
-    double nv[kPer];
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int idx = t + e * NT;
-      nv[e] = 0.0;
-      if (idx < KK * KK) {
-        const int i = idx / KK, l = idx - i * KK;
-        const double wil = Gi[i * KS + l], wij = Gi[i * KS + j], wlj = Gi[l * KS + j];
-        if (i == j) {
-          nv[e] = l == j ? -inv : wil * inv;
-        } else {
-          const double m = wij * inv;
-          nv[e] = l == j ? m : wil - m * wlj;
-        }
-      }
+      const int i = wr + e * SR;
+      const double m = wij[e] * inv;
+      const double off_row = wl == j ? m : w[e] - m * wlj;
+      const double piv_row = wl == j ? -inv : w[e] * inv;
+      w[e] = i == j ? piv_row : off_row;
     }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int idx = t + e * NT;
-      if (idx < KK * KK) Gi[(idx / KK) * KS + idx % KK] = nv[e];
-    }
-    __syncthreads();
   }
-  {
-    double nv[kPer];
+  // Gi[q][p] = -W[p][q] on U x U, zero elsewhere (and the transposed copy)
+  if (wown) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int idx = t + e * NT;
-      nv[e] = 0.0;
-      if (idx < KK * KK) {
-        const int q = idx / KK, pl = idx - q * KK;
-        const bool inU = q < k && pl < k && !((pinned0 >> q) & 1ull) && !((pinned0 >> pl) & 1ull);
-        nv[e] = inU ? -Gi[pl * KS + q] : 0.0;
+      const int i = wr + e * SR;
+      if (i < KK) {
+        const bool inU = wl < k && i < k && !((pinned0 >> wl) & 1ull) && !((pinned0 >> i) & 1ull);
+        const double v = inU ? -w[e] : 0.0;
+        Gi[wl * KS + i] = v;
+        if constexpr (PairShared<KK>::kT) sh.GiT[i * PairShared<KK>::KT + wl] = v;
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int idx = t + e * NT;
-      if (idx < KK * KK) {
-        Gi[(idx / KK) * KS + idx % KK] = nv[e];
-        if constexpr (PairShared<KK>::kT) sh.GiT[(idx % KK) * PairShared<KK>::KT + idx / KK] = nv[e];
-      }
-    }
-    __syncthreads();
   }
-
+  __syncthreads();
   uint32_t* pc = gs.pcnt;
   unsigned long long* tg = gs.tot;
   int* pw = gs.pix;
