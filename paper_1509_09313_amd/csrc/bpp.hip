@@ -719,23 +719,25 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     if (Gs[q * KS + q] <= 1e-14 * dmax) pinned0 |= bit64(q);
 
   // G_U^{-1} by the symmetric sweep over the unpinned indices in index order,
-  // on a row-major working copy W: sweeping j maps W_jj -> -1/d,
+  // on a row-major working copy W of the leading k x k block of G (the
+  // identity padding never mixes with it): sweeping j maps W_jj -> -1/d,
   // W_jl -> W_jl / d, W_ij -> W_ij / d and W_il -> W_il - (W_ij / d) W_lj
-  // (d = W_jj), as the one-row-per-lane form does with one row per lane; then
-  // (G_U^{-1})_{q,p} = -W[p][q] on U x U.  Thread t keeps the entries
-  // (i, l) = (t / KK + e SR, t % KK), e < kPer, in registers through the whole
-  // sweep; a step needs only the old column j (W_ij, W_lj and d), which its
-  // owners publish in one of two LDS buffers (alternating, so one barrier per
-  // step suffices).
-  constexpr int SR = (KK + kPer - 1) / kPer;  // row groups: KK * SR <= NT
-  static_assert(KK * SR <= NT, "every entry of W has an owner");
-  const int wl = t % KK, wr = t / KK;
-  const bool wown = t < KK * SR;
+  // (d = W_jj), as the one-row-per-lane form does with one row per lane;
+  // then (G_U^{-1})_{q,p} = -W[p][q] on U x U.  Thread t keeps the entries
+  // (i, l) = (t / k + e sr, t % k), e < kPer, in registers through the whole
+  // sweep; a step needs only the old column j, which its owners publish in
+  // one of two LDS buffers (alternating, so one barrier per step suffices).
+  // Wavefronts without entries only keep the barriers.
+  static_assert(KK * ((KK + kPer - 1) / kPer) <= NT, "every entry of W has an owner");
+  const int sr = (k + kPer - 1) / kPer;  // row groups: k * sr <= NT
+  const int wl = t % k, wr = t / k;
+  const bool wown = t < k * sr;
+  const bool wave_own = __builtin_amdgcn_readfirstlane(t >> 6) * 64 < k * sr;
   double w[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
-    const int i = wr + e * SR;
-    w[e] = (wown && i < KK) ? Gs[i * KS + wl] : 0.0;
+    const int i = wr + e * sr;
+    w[e] = (wown && i < k) ? Gs[i * KS + wl] : 0.0;
   }
   bool inv_ok = true;
   int par = 0;
@@ -746,47 +748,58 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
     if (wown && wl == j) {
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        const int i = wr + e * SR;
-        if (i < KK) cb[i] = w[e];
+        const int i = wr + e * sr;
+        if (i < k) cb[i] = w[e];
       }
     }
     __syncthreads();
-    // (every read of the step is issued here, and the update is branch-free;
-    // entries past KK and threads without entries compute values that are
-    // never stored)
+    // every thread takes the pivot test (the same in all of them)
     const double d = cb[j];
-    const double wlj = cb[wl];
-    double wij[kPer];
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int i = wr + e * SR;
-      wij[e] = cb[i < KK ? i : 0];
-    }
     if (!(d > 1e-6 * Gs[j * KS + j])) inv_ok = false;
-    const double inv = 1.0 / d;
+    if (wave_own) {
+      // (every read of the step is issued here, and the update is
+      // branch-free; entries past k and lanes without entries compute values
+      // that are never stored)
+      const double wlj = cb[wown ? wl : 0];
+      double wij[kPer];
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int i = wr + e * SR;
-      const double m = wij[e] * inv;
-      const double off_row = wl == j ? m : w[e] - m * wlj;
-      const double piv_row = wl == j ? -inv : w[e] * inv;
-      w[e] = i == j ? piv_row : off_row;
+      for (int e = 0; e < kPer; ++e) {
+        const int i = wr + e * sr;
+        wij[e] = cb[(wown && i < k) ? i : 0];
+      }
+      const double inv = 1.0 / d;
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int i = wr + e * sr;
+        const double m = wij[e] * inv;
+        const double off_row = wl == j ? m : w[e] - m * wlj;
+        const double piv_row = wl == j ? -inv : w[e] * inv;
+        w[e] = i == j ? piv_row : off_row;
+      }
     }
   }
   // Gi[q][p] = -W[p][q] on U x U, zero elsewhere (and the transposed copy)
   if (wown) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int i = wr + e * SR;
-      if (i < KK) {
-        const bool inU = wl < k && i < k && !((pinned0 >> wl) & 1ull) && !((pinned0 >> i) & 1ull);
+      const int i = wr + e * sr;
+      if (i < k) {
+        const bool inU = !((pinned0 >> wl) & 1ull) && !((pinned0 >> i) & 1ull);
         const double v = inU ? -w[e] : 0.0;
         Gi[wl * KS + i] = v;
         if constexpr (PairShared<KK>::kT) sh.GiT[i * PairShared<KK>::KT + wl] = v;
       }
     }
   }
+  for (int idx = t; idx < KK * KK; idx += NT) {
+    const int q = idx / KK, pp = idx - q * KK;
+    if (q >= k || pp >= k) {
+      Gi[q * KS + pp] = 0.0;
+      if constexpr (PairShared<KK>::kT) sh.GiT[pp * PairShared<KK>::KT + q] = 0.0;
+    }
+  }
   __syncthreads();
+
   uint32_t* pc = gs.pcnt;
   unsigned long long* tg = gs.tot;
   int* pw = gs.pix;
