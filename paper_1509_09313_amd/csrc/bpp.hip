@@ -630,6 +630,7 @@ struct PairShared {
   alignas(16) double GiT[kT ? KK * KT : 2];
   Grp grps[NW][P];
   double dsum[NW];
+  int inv_ok_s;  // every sweep pivot passed the test (G_U^{-1} usable)
   // the sweep's pivot column, in two alternating buffers
   double colbuf[2][KK];
 
@@ -673,14 +674,16 @@ struct PairShared {
 // Solves problems [b0, b1) of one G: problem group g (P problems, one per
 // L lanes) for g = g_first, g_first + g_step, ...  Loads G and runs the sweep
 // first (after a barrier, so a persistent loop may call it again with
-// another G); adds its statistics to sh.
+// another G), unless `reuse` says that sh already holds this G, its
+// G_U^{-1} and its pivot test from the block's previous call; adds its
+// statistics to sh.
 template <int KK>
 __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const double* __restrict__ G,
                                            const float* __restrict__ R, int64_t ldr, float* __restrict__ X,
                                            int64_t ldx, const uint64_t* mask_in, uint64_t* mask_out,
                                            uint8_t* __restrict__ rounds_out, uint8_t* __restrict__ status_out,
                                            int max_rounds, int warm_cap, int64_t b0, int64_t b1, int64_t g_first,
-                                           int64_t g_step) {
+                                           int64_t g_step, bool reuse = false) {
   constexpr int L = pair_lanes(KK);  // lanes per problem
   constexpr int P = 64 / L;          // problems per wavefront
   constexpr int NP = KK / 2;         // pivot positions: k <= KK, so at most KK / 2 pivots
@@ -705,12 +708,14 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
   const int c1 = i1 < KK ? i1 : KK - 1;
 
   __syncthreads();
-  for (int idx = t; idx < KK * KK; idx += NT) {
-    const int q = idx / KK, pp = idx - q * KK;
-    const double v = (q < k && pp < k) ? G[q * k + pp] : (q == pp ? 1.0 : 0.0);
-    Gs[q * KS + pp] = v;
+  if (!reuse) {
+    for (int idx = t; idx < KK * KK; idx += NT) {
+      const int q = idx / KK, pp = idx - q * KK;
+      const double v = (q < k && pp < k) ? G[q * k + pp] : (q == pp ? 1.0 : 0.0);
+      Gs[q * KS + pp] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const uint64_t all = (k == 64) ? ~0ull : (bit64(k) - 1ull);
   double dmax = 0.0;
   for (int q = 0; q < k; ++q) dmax = fmax(dmax, Gs[q * KS + q]);
@@ -729,76 +734,80 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
   // one of two LDS buffers (alternating, so one barrier per step suffices).
   // Wavefronts without entries only keep the barriers.
   static_assert(KK * ((KK + kPer - 1) / kPer) <= NT, "every entry of W has an owner");
-  const int sr = (k + kPer - 1) / kPer;  // row groups: k * sr <= NT
-  const int wl = t % k, wr = t / k;
-  const bool wown = t < k * sr;
-  const bool wave_own = __builtin_amdgcn_readfirstlane(t >> 6) * 64 < k * sr;
-  double w[kPer];
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    const int i = wr + e * sr;
-    w[e] = (wown && i < k) ? Gs[i * KS + wl] : 0.0;
-  }
-  bool inv_ok = true;
-  int par = 0;
-  for (int j = 0; j < k; ++j) {
-    if ((pinned0 >> j) & 1ull) continue;
-    double* cb = sh.colbuf[par];
-    par ^= 1;
-    if (wown && wl == j) {
-#pragma unroll
-      for (int e = 0; e < kPer; ++e) {
-        const int i = wr + e * sr;
-        if (i < k) cb[i] = w[e];
-      }
-    }
-    __syncthreads();
-    // every thread takes the pivot test (the same in all of them)
-    const double d = cb[j];
-    if (!(d > 1e-6 * Gs[j * KS + j])) inv_ok = false;
-    if (wave_own) {
-      // (every read of the step is issued here, and the update is
-      // branch-free; entries past k and lanes without entries compute values
-      // that are never stored)
-      const double wlj = cb[wown ? wl : 0];
-      double wij[kPer];
-#pragma unroll
-      for (int e = 0; e < kPer; ++e) {
-        const int i = wr + e * sr;
-        wij[e] = cb[(wown && i < k) ? i : 0];
-      }
-      const double inv = 1.0 / d;
-#pragma unroll
-      for (int e = 0; e < kPer; ++e) {
-        const int i = wr + e * sr;
-        const double m = wij[e] * inv;
-        const double off_row = wl == j ? m : w[e] - m * wlj;
-        const double piv_row = wl == j ? -inv : w[e] * inv;
-        w[e] = i == j ? piv_row : off_row;
-      }
-    }
-  }
-  // Gi[q][p] = -W[p][q] on U x U, zero elsewhere (and the transposed copy)
-  if (wown) {
+  if (!reuse) {
+    bool inv_ok = true;
+    const int sr = (k + kPer - 1) / kPer;  // row groups: k * sr <= NT
+    const int wl = t % k, wr = t / k;
+    const bool wown = t < k * sr;
+    const bool wave_own = __builtin_amdgcn_readfirstlane(t >> 6) * 64 < k * sr;
+    double w[kPer];
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int i = wr + e * sr;
-      if (i < k) {
-        const bool inU = !((pinned0 >> wl) & 1ull) && !((pinned0 >> i) & 1ull);
-        const double v = inU ? -w[e] : 0.0;
-        Gi[wl * KS + i] = v;
-        if constexpr (PairShared<KK>::kT) sh.GiT[i * PairShared<KK>::KT + wl] = v;
+      w[e] = (wown && i < k) ? Gs[i * KS + wl] : 0.0;
+    }
+    int par = 0;
+    for (int j = 0; j < k; ++j) {
+      if ((pinned0 >> j) & 1ull) continue;
+      double* cb = sh.colbuf[par];
+      par ^= 1;
+      if (wown && wl == j) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+          const int i = wr + e * sr;
+          if (i < k) cb[i] = w[e];
+        }
+      }
+      __syncthreads();
+      // every thread takes the pivot test (the same in all of them)
+      const double d = cb[j];
+      if (!(d > 1e-6 * Gs[j * KS + j])) inv_ok = false;
+      if (wave_own) {
+        // (every read of the step is issued here, and the update is
+        // branch-free; entries past k and lanes without entries compute values
+        // that are never stored)
+        const double wlj = cb[wown ? wl : 0];
+        double wij[kPer];
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+          const int i = wr + e * sr;
+          wij[e] = cb[(wown && i < k) ? i : 0];
+        }
+        const double inv = 1.0 / d;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+          const int i = wr + e * sr;
+          const double m = wij[e] * inv;
+          const double off_row = wl == j ? m : w[e] - m * wlj;
+          const double piv_row = wl == j ? -inv : w[e] * inv;
+          w[e] = i == j ? piv_row : off_row;
+        }
       }
     }
-  }
-  for (int idx = t; idx < KK * KK; idx += NT) {
-    const int q = idx / KK, pp = idx - q * KK;
-    if (q >= k || pp >= k) {
-      Gi[q * KS + pp] = 0.0;
-      if constexpr (PairShared<KK>::kT) sh.GiT[pp * PairShared<KK>::KT + q] = 0.0;
+    // Gi[q][p] = -W[p][q] on U x U, zero elsewhere (and the transposed copy)
+    if (wown) {
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int i = wr + e * sr;
+        if (i < k) {
+          const bool inU = !((pinned0 >> wl) & 1ull) && !((pinned0 >> i) & 1ull);
+          const double v = inU ? -w[e] : 0.0;
+          Gi[wl * KS + i] = v;
+          if constexpr (PairShared<KK>::kT) sh.GiT[i * PairShared<KK>::KT + wl] = v;
+        }
+      }
     }
+    for (int idx = t; idx < KK * KK; idx += NT) {
+      const int q = idx / KK, pp = idx - q * KK;
+      if (q >= k || pp >= k) {
+        Gi[q * KS + pp] = 0.0;
+        if constexpr (PairShared<KK>::kT) sh.GiT[pp * PairShared<KK>::KT + q] = 0.0;
+      }
+    }
+    if (t == 0) sh.inv_ok_s = inv_ok ? 1 : 0;
   }
   __syncthreads();
+  const bool inv_ok = sh.inv_ok_s != 0;
 
   uint32_t* pc = gs.pcnt;
   unsigned long long* tg = gs.tot;
@@ -1123,10 +1132,18 @@ k_bpp_pair_grouped(const nmf::BppItem* __restrict__ items, int64_t n, int max_ro
   __shared__ PairShared<KK> sh;
   constexpr int NW = pair_waves(KK);
   sh.clear_stats();
-  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+  // a contiguous range of items per block: the items of one instance are
+  // adjacent, so most calls find their G already loaded and swept
+  const int64_t i0 = (int64_t)blockIdx.x * n / gridDim.x, i1 = ((int64_t)blockIdx.x + 1) * n / gridDim.x;
+  const double* prevG = nullptr;
+  int prevk = 0;
+  for (int64_t i = i0; i < i1; ++i) {
     const nmf::BppItem it = items[i];
+    const bool reuse = it.G == prevG && it.k == prevk;
     pair_block<KK>(sh, it.k, it.G, it.R, it.ldr, it.X, it.ldx, it.mask, it.mask, nullptr, it.status, max_rounds,
-                   warm_cap, it.b0, it.b1, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), NW);
+                   warm_cap, it.b0, it.b1, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), NW, reuse);
+    prevG = it.G;
+    prevk = it.k;
   }
   sh.flush(counters, nullptr, nullptr);
 }
