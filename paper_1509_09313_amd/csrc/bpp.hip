@@ -25,9 +25,9 @@
 // columns are packed at the end of the row (see the elimination), so a step
 // touches only later pivots.
 //
-// Two forms of the same passive-set solve.  Each block also sweeps G once
-// (symmetric sweep operator over the unpinned indices U, FP64, index order)
-// to get G_U^{-1} in LDS, and each problem forms z = G_U^{-1} f.  When the
+// Two forms of the same passive-set solve.  Each block also sweeps each G it
+// serves once (symmetric sweep operator over the unpinned indices U, FP64,
+// index order) to get G_U^{-1} in LDS, and each problem forms z = G_U^{-1} f.  When the
 // active part A = U \ F is smaller than F, the round eliminates over A on
 // (G^{-1}, z) instead of over F on (G, f): with v = ((G^{-1})_AA)^{-1} z_A,
 //     x_F = z_F - (G^{-1})_FA v       y_A = -v
