@@ -926,6 +926,18 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       const double* Mrow = useInv ? Gi : Gs;
       const int np = __popcll(Pv);
       const int off = NP - np;
+      // the first position that any problem of the wavefront uses, made
+      // wave-uniform for the classes with up to four problems per wavefront:
+      // a position before it then costs one scalar compare instead of a
+      // ballot (the smaller classes, with four or eight positions, ballot)
+      constexpr bool kFirst = P <= 4;
+      int first = 0;
+      if constexpr (kFirst) {
+        int npw = 0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) npw = max(npw, __builtin_amdgcn_readlane(np, q * L));
+        first = NP - npw;
+      }
       bool retry = false;
       // each owned pivot enters its index, right-hand side and diagonal at
       // its packed position
@@ -945,17 +957,26 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
         if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
-        // positions before the pivots are never read; they load row 0.  (The
-        // position tests of the three loops use an opaque copy of c, so the
-        // compiler does not keep NP lane masks alive through the round.)
+        // positions before every problem's first pivot are skipped (zero, so
+        // that no value is carried between rounds)
+        if constexpr (kFirst) {
+          if (c < first) {
+            r[c] = 0.0;
+            continue;
+          }
+        }
+        // positions before a problem's own pivots are never read; they load
+        // row 0.  (The position tests of the three loops use an opaque copy of
+        // c, so the compiler does not keep NP lane masks alive through the
+        // round.)
         int cs = c;
         asm volatile("" : "+s"(cs));
         const bool act = cs >= off;
-        // positions before every problem's first pivot are skipped (zero, so
-        // that no value is carried between rounds)
-        if (__ballot(act) == 0ull) {
-          r[c] = 0.0;
-          continue;
+        if constexpr (!kFirst) {
+          if (__ballot(act) == 0ull) {
+            r[c] = 0.0;
+            continue;
+          }
         }
         const int jc = act ? pw[c] : 0;
         r[c] = Mrow[jc * KS + jh];
@@ -965,10 +986,15 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       wave_lds_sync();
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
+        if constexpr (kFirst) {
+          if (c < first) continue;
+        }
         int cs = c;
         asm volatile("" : "+s"(cs));
         const bool act = cs >= off;
-        if (__ballot(act) == 0ull) continue;
+        if constexpr (!kFirst) {
+          if (__ballot(act) == 0ull) continue;
+        }
         const bool pl = h == cs;  // this step's pivot lane
         colw[h] = r[c];
         rfw[h] = rf;
@@ -1014,10 +1040,15 @@ __device__ __forceinline__ void pair_block(PairShared<KK>& sh, int k, const doub
       double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
+        if constexpr (kFirst) {
+          if (c < first) continue;
+        }
         int cs = c;
         asm volatile("" : "+s"(cs));
         const bool act = cs >= off;
-        if (__ballot(act) == 0ull) continue;
+        if constexpr (!kFirst) {
+          if (__ballot(act) == 0ull) continue;
+        }
         if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
         const int jc = act ? pw[c] : 0;
         const double vc = vw[c];
